@@ -1,0 +1,239 @@
+/*
+ * sp2dm.h -- C ABI of the MI355X (gfx950) SP2 / SP2ACC density-matrix library.
+ *
+ * The library computes the zero-temperature density matrix D = theta(mu I - F)
+ * of a symmetric block-sparse Fock/Kohn-Sham matrix F by the recursive
+ * second-order spectral projection expansion with scale-and-fold acceleration
+ * and error-controlled truncation, following Kruchinina, Rudberg, Rubensson,
+ * "Efficient computation of the density matrix with error control on
+ * distributed computer systems" (arXiv:1909.12533):
+ *   - problem statement: F symmetric, n_occ occupied orbitals, a non-zero
+ *     homo-lumo gap, D = sum_{i<=n_occ} y_i y_i^T (section "Introduction");
+ *   - Step 1 / Algorithm 1 / Algorithm 2 / Step 3 of section "Density matrix
+ *     construction" (schedule, initialisation, iteration with truncation and
+ *     parameterless stopping, homo/lumo estimates);
+ *   - truncation thresholds of eq. (tau_trunc) and the bound on the
+ *     occupied-subspace error (section "Error control");
+ *   - Frobenius and Frob-Inf truncation norms (section "Upper bounds for the
+ *     spectral norm");
+ *   - symmetric storage of the upper triangle only (section "Implementation
+ *     details").
+ *
+ * Every operation runs on the GPU in hand-written HIP kernels; the host only
+ * sequences them and evaluates scalar formulas (schedule, stopping test,
+ * homo/lumo back-propagation, error bookkeeping) in IEEE double precision.
+ *
+ * Conventions
+ * -----------
+ * Matrices are "upper BSR" (sp2_bsr): n x n, block size bs = 64 (the only
+ * supported value), nbr = ceil(n / 64) block rows, nnzb stored blocks (I, J)
+ * with J >= I, sorted by (I, J); row_ptr[nbr + 1] (int64), col_idx[nnzb]
+ * (int32), val[nnzb * 64 * 64] (double, each block row-major).  A block below
+ * the diagonal is the transpose of its stored mirror; diagonal blocks are
+ * full symmetric 64 x 64 blocks.  When n is not a multiple of 64, rows and
+ * columns >= n of the last block row/column are padding and must be 0.
+ * All pointers inside sp2_bsr are DEVICE pointers on the context's device.
+ *
+ * Ownership: inputs are borrowed; they must stay valid until the call returns
+ * (every call is synchronous with respect to the host: it returns after the
+ * context's stream has finished the work it issued).  Matrices returned
+ * through "sp2_bsr **out" are allocated by the library (through the allocator
+ * installed with sp2_set_allocator, or hipMalloc) and released with
+ * sp2_bsr_free.  A tape is released with sp2_tape_free.
+ *
+ * Return codes: 0 = success; negative = error, no output written (*out left
+ * NULL), message in sp2_last_error; positive = warning, outputs valid.
+ * A context is not thread-safe; use one context per host thread / stream.
+ */
+#ifndef SP2DM_H
+#define SP2DM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SP2_OK 0
+#define SP2_ERR_INVALID_ARG (-1) /* n_occ not in (0, n), bs != 64, lmin >= lmax, bad pattern ... */
+#define SP2_ERR_BAD_BOUNDS (-2)  /* not (lmin <= homo_ub < lumo_lb <= lmax) */
+#define SP2_ERR_NONFINITE (-3)   /* F (or another input) holds NaN / Inf */
+#define SP2_ERR_OOM (-4)         /* device allocation failed */
+#define SP2_ERR_HIP (-5)         /* HIP runtime error */
+#define SP2_WARN_NOT_CONVERGED 1 /* n_max reached before the stopping criterion fired */
+#define SP2_WARN_TRACE 2         /* |tr D - n_occ| > 1/2: bounds wrong or gap closed */
+
+#define SP2_BLOCK 64
+
+/* precision of the bulk squares */
+#define SP2_PREC_FP64 0   /* every square in FP64 MFMA */
+#define SP2_PREC_FP32 1   /* FP32 MFMA squares (FP32 storage) until e_i < switch_tol, then FP64 */
+#define SP2_PREC_BF16X3 2 /* BF16 hi/lo split MFMA (hi*hi + hi*lo + lo*hi, FP32 accumulate), then FP64 */
+
+/* truncation norm (section "Upper bounds for the spectral norm") */
+#define SP2_TRUNC_NONE 0
+#define SP2_TRUNC_FROB 1
+#define SP2_TRUNC_FROBINF 2
+
+/* stop reasons */
+#define SP2_STOP_CRITERION 1   /* e_i > C e_{i-2}^2 with p_i != p_{i-1} (Algorithm 2) */
+#define SP2_STOP_IDEMPOTENCY 2 /* e_i <= idem_stop */
+#define SP2_STOP_NMAX 3        /* i = n_max */
+
+typedef struct sp2_ctx sp2_ctx;
+typedef struct sp2_tape sp2_tape;
+
+typedef struct {
+  int64_t n;        /* matrix dimension */
+  int32_t bs;       /* block size, must be 64 */
+  int32_t owned;    /* 1: allocated by the library, release with sp2_bsr_free */
+  int64_t nbr;      /* ceil(n / bs) */
+  int64_t nnzb;     /* stored blocks */
+  int64_t *row_ptr; /* device, nbr + 1 */
+  int32_t *col_idx; /* device, nnzb */
+  double *val;      /* device, nnzb * bs * bs */
+} sp2_bsr;
+
+typedef struct {
+  int32_t accel;        /* 1: SP2ACC (scale-and-fold), 0: SP2 (alpha_i = 1, n_min = 1) */
+  int32_t precision;    /* SP2_PREC_* */
+  double switch_tol;    /* mixed precision: FP64 from the first square after e_i < switch_tol */
+  int32_t trunc_norm;   /* SP2_TRUNC_* */
+  int32_t n_max_cap;    /* cap of n_max, and n_max of the trace-correcting run (<= 1000) */
+  int64_t coarse_bs;    /* Frob-Inf submatrix size, a multiple of 64 (paper: 4096) */
+  double gamma;         /* allowed occupied-subspace error, eq. (tau_trunc); used when tau_fixed == 0 */
+  double tau_fixed;     /* > 0: the same threshold tau for every iteration */
+  double idem_stop;     /* > 0: also stop when e_i <= idem_stop */
+  int32_t record_tape;  /* 1: keep the masks and checkpoints needed by vjp / jvp / replay */
+  int32_t n_checkpoints;/* number of X~_i checkpoints in the tape; 0 = ceil(sqrt(n)) */
+} sp2_options;
+
+/* Per-run statistics.  Arrays are HOST arrays owned by the caller, each of
+ * length `capacity` (>= n_max_cap + 1); entry i refers to X~_i.  Any array
+ * pointer may be NULL. */
+typedef struct {
+  int32_t capacity;
+  int32_t n_iter;       /* n: D = X~_n */
+  int32_t n_max, n_min;
+  int32_t stop_reason;  /* SP2_STOP_* */
+  int32_t switch_iter;  /* mixed precision: first iteration squared in FP64 (-1: none) */
+  double homo_ub_est;   /* Step 3 estimates (NaN when no iteration qualified) */
+  double lumo_lb_est;
+  double subspace_err_bound; /* sum_i ||E_i||_M / (xi_i - ||E_i||_M) ("Error control"); NaN without bounds */
+  double time_s;        /* wall time of the expansion (device resident input to device resident D) */
+  double alg_flops;     /* sum_i 2 * 64^3 * #{(I,K,J): I <= J, X~_IK != 0 != X~_KJ} */
+  int64_t max_nnzb;
+  double *e;            /* ||X~_i - X~_i^2||_F */
+  double *t;            /* tr(X~_i - X~_i^2) */
+  double *trace;        /* tr X~_i */
+  double *alpha;
+  double *tau;
+  double *trunc_err_frob;  /* ||E_i||_F */
+  double *trunc_err_mixed; /* ||E_i||_M */
+  double *iter_time_s;
+  double *iter_flops;
+  int32_t *p;
+  int32_t *precision;   /* precision of the square of X~_i */
+  int64_t *nnzb;        /* stored upper blocks of X~_i */
+  double *square_time_s;   /* device time of the MFMA square of X~_i (HIP events on the context stream) */
+  double square_time_total_s; /* sum of square_time_s over the run */
+} sp2_stats;
+
+typedef void *(*sp2_alloc_fn)(size_t bytes, void *user);
+typedef void (*sp2_free_fn)(void *ptr, void *user);
+
+/* Library version string. */
+const char *sp2_version(void);
+
+/* Fill *opt with the defaults: SP2ACC, FP64, switch_tol 1e-3, Frob-Inf,
+ * n_max_cap 100, coarse_bs 4096, gamma 1e-3, tau_fixed 0, idem_stop 0,
+ * no tape. */
+void sp2_options_default(sp2_options *opt);
+
+/* Create a context on HIP device `device` issuing all work on `hip_stream`
+ * (a hipStream_t; NULL = the null stream).  Returns SP2_ERR_HIP when the
+ * device cannot be used. */
+int sp2_create(sp2_ctx **ctx, int device, void *hip_stream);
+void sp2_destroy(sp2_ctx *ctx);
+
+/* Route every device allocation of the library through (alloc, free_).
+ * alloc must return device memory on the context's device usable on its
+ * stream, or NULL on failure.  NULL restores hipMalloc / hipFree.  Buffers
+ * cached by the context are released first. */
+int sp2_set_allocator(sp2_ctx *ctx, sp2_alloc_fn alloc, sp2_free_fn free_, void *user);
+
+/* Release device buffers cached between calls. */
+void sp2_trim(sp2_ctx *ctx);
+
+/* Message of the last error on this context ("" when none). */
+const char *sp2_last_error(const sp2_ctx *ctx);
+
+/* Gershgorin interval [lmin, lmax] containing the spectrum of F (Step 1:
+ * lambda_min <= lambda_1 and lambda_max >= lambda_N). */
+int sp2_gershgorin(sp2_ctx *ctx, const sp2_bsr *F, double *lmin, double *lmax);
+
+/* Density matrix by SP2 / SP2ACC (Steps 1-3, Algorithms 1-2).
+ *   F         symmetric input in upper BSR (device)
+ *   n_occ     number of occupied orbitals, 0 < n_occ < n
+ *   lmin/lmax spectral bounds, lmin <= lambda_1, lmax >= lambda_N
+ *   homo_ub, lumo_lb  pointers to bounds homo <= *homo_ub < *lumo_lb <= lumo,
+ *             or both NULL: trace-correcting run (alpha = 1, p_i from traces,
+ *             thresholds tau_fixed), the first run of the paper's protocol
+ *   opt       options (NULL = defaults)
+ *   D_out     receives D = X~_n (library-owned upper BSR)
+ *   homo_est, lumo_est  receive updated bounds from Step 3 (NaN if none)
+ *   stats     optional per-iteration statistics (caller-owned host arrays)
+ *   tape      optional: receives the tape for sp2_vjp / sp2_jvp / sp2_replay
+ *             (requires opt->record_tape = 1)
+ * Returns 0, a warning (> 0) or an error (< 0). */
+int sp2_density(sp2_ctx *ctx, const sp2_bsr *F, int64_t n_occ, double lmin, double lmax,
+                const double *homo_ub, const double *lumo_lb, const sp2_options *opt,
+                sp2_bsr **D_out, double *homo_est, double *lumo_est, sp2_stats *stats,
+                sp2_tape **tape);
+
+/* Vector-Jacobian product of the recorded (frozen schedule and masks) map
+ * F -> D: Fbar = (dL/dF) for L = tr(W D), W symmetric in upper BSR on any
+ * pattern.  X~_i are recomputed from the tape's checkpoints. */
+int sp2_vjp(sp2_ctx *ctx, const sp2_tape *tape, const sp2_bsr *W, sp2_bsr **Fbar_out);
+
+/* Jacobian-vector product dD = (dD/dF) dF of the recorded map. */
+int sp2_jvp(sp2_ctx *ctx, const sp2_tape *tape, const sp2_bsr *dF, sp2_bsr **dD_out);
+
+/* The recorded map applied to another F (same n): schedule, n and masks
+ * frozen.  Used for finite differences. */
+int sp2_replay(sp2_ctx *ctx, const sp2_tape *tape, const sp2_bsr *F, sp2_bsr **D_out);
+
+/* Tape facts: number of iterations, checkpoints held, bytes held on the device. */
+int sp2_tape_info(const sp2_tape *tape, int32_t *n_iter, int32_t *n_checkpoints, int64_t *device_bytes);
+
+/* ---- single steps of the hot path (kernel-level entry points) ---------- */
+
+/* One square of Algorithm 2 on an upper-BSR X: S = X^2 on the block pattern
+ * of the square (every (I, J), I <= J, with some K such that X_IK and X_KJ
+ * are stored), and Xn = a I + b X + c S on that pattern, where the a I term
+ * touches only the n real diagonal entries.  sums[0] = ||X - S||_F^2,
+ * sums[1] = tr X, sums[2] = tr S, sums[3] = algorithmic flops
+ * (2 * 64^3 per block product).  precision: SP2_PREC_* (FP32 and BF16X3 round X
+ * to FP32 first and return Xn rounded to FP32 values). */
+int sp2_square_step(sp2_ctx *ctx, const sp2_bsr *X, double a, double b, double c, int precision,
+                    sp2_bsr **Xn_out, double sums[4]);
+
+/* Truncation X~ = X + E with ||E|| <= tau in the chosen norm (section "Error
+ * control"); diagonal blocks are never removed.  err[0] = ||E||_F,
+ * err[1] = ||E||_M with submatrices of coarse_bs rows. */
+int sp2_truncate(sp2_ctx *ctx, const sp2_bsr *X, double tau, int norm, int64_t coarse_bs,
+                 sp2_bsr **Xt_out, double err[2]);
+
+/* Copy a library matrix into caller buffers (device pointers of sizes
+ * nbr + 1, nnzb, nnzb * 64 * 64). */
+int sp2_bsr_copy(sp2_ctx *ctx, const sp2_bsr *src, int64_t *row_ptr, int32_t *col_idx, double *val);
+
+void sp2_bsr_free(sp2_ctx *ctx, sp2_bsr *m);
+void sp2_tape_free(sp2_ctx *ctx, sp2_tape *tape);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SP2DM_H */

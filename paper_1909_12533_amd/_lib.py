@@ -1,0 +1,151 @@
+"""ctypes declarations of the C ABI in ``include/sp2dm.h``."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsp2dm.so")
+
+SP2_OK = 0
+SP2_ERR_INVALID_ARG = -1
+SP2_ERR_BAD_BOUNDS = -2
+SP2_ERR_NONFINITE = -3
+SP2_ERR_OOM = -4
+SP2_ERR_HIP = -5
+SP2_WARN_NOT_CONVERGED = 1
+SP2_WARN_TRACE = 2
+
+PREC_FP64, PREC_FP32, PREC_BF16X3 = 0, 1, 2
+TRUNC_NONE, TRUNC_FROB, TRUNC_FROBINF = 0, 1, 2
+STOP_CRITERION, STOP_IDEMPOTENCY, STOP_NMAX = 1, 2, 3
+
+# names of every exported entry point declared in include/sp2dm.h
+EXPORTS = [
+    "sp2_version", "sp2_options_default", "sp2_create", "sp2_destroy", "sp2_set_allocator", "sp2_trim",
+    "sp2_last_error", "sp2_gershgorin", "sp2_density", "sp2_vjp", "sp2_jvp", "sp2_replay", "sp2_tape_info",
+    "sp2_square_step", "sp2_truncate", "sp2_bsr_copy", "sp2_bsr_free", "sp2_tape_free",
+]
+
+
+class sp2_bsr(C.Structure):
+    _fields_ = [
+        ("n", C.c_int64),
+        ("bs", C.c_int32),
+        ("owned", C.c_int32),
+        ("nbr", C.c_int64),
+        ("nnzb", C.c_int64),
+        ("row_ptr", C.c_void_p),
+        ("col_idx", C.c_void_p),
+        ("val", C.c_void_p),
+    ]
+
+
+class sp2_options(C.Structure):
+    _fields_ = [
+        ("accel", C.c_int32),
+        ("precision", C.c_int32),
+        ("switch_tol", C.c_double),
+        ("trunc_norm", C.c_int32),
+        ("n_max_cap", C.c_int32),
+        ("coarse_bs", C.c_int64),
+        ("gamma", C.c_double),
+        ("tau_fixed", C.c_double),
+        ("idem_stop", C.c_double),
+        ("record_tape", C.c_int32),
+        ("n_checkpoints", C.c_int32),
+    ]
+
+
+_DP = C.POINTER(C.c_double)
+_IP = C.POINTER(C.c_int32)
+_LP = C.POINTER(C.c_int64)
+
+
+class sp2_stats(C.Structure):
+    _fields_ = [
+        ("capacity", C.c_int32),
+        ("n_iter", C.c_int32),
+        ("n_max", C.c_int32),
+        ("n_min", C.c_int32),
+        ("stop_reason", C.c_int32),
+        ("switch_iter", C.c_int32),
+        ("homo_ub_est", C.c_double),
+        ("lumo_lb_est", C.c_double),
+        ("subspace_err_bound", C.c_double),
+        ("time_s", C.c_double),
+        ("alg_flops", C.c_double),
+        ("max_nnzb", C.c_int64),
+        ("e", _DP),
+        ("t", _DP),
+        ("trace", _DP),
+        ("alpha", _DP),
+        ("tau", _DP),
+        ("trunc_err_frob", _DP),
+        ("trunc_err_mixed", _DP),
+        ("iter_time_s", _DP),
+        ("iter_flops", _DP),
+        ("p", _IP),
+        ("precision", _IP),
+        ("nnzb", _LP),
+        ("square_time_s", _DP),
+        ("square_time_total_s", C.c_double),
+    ]
+
+
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load the HIP library; raises when it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(
+            f"HIP library {path} is missing: build it first (python -m paper_1909_12533_amd.build)")
+    lib = C.CDLL(path)
+    P = C.POINTER
+    lib.sp2_version.restype = C.c_char_p
+    lib.sp2_version.argtypes = []
+    lib.sp2_options_default.restype = None
+    lib.sp2_options_default.argtypes = [P(sp2_options)]
+    lib.sp2_create.restype = C.c_int
+    lib.sp2_create.argtypes = [P(C.c_void_p), C.c_int, C.c_void_p]
+    lib.sp2_destroy.restype = None
+    lib.sp2_destroy.argtypes = [C.c_void_p]
+    lib.sp2_set_allocator.restype = C.c_int
+    lib.sp2_set_allocator.argtypes = [C.c_void_p, ALLOC_FN, FREE_FN, C.c_void_p]
+    lib.sp2_trim.restype = None
+    lib.sp2_trim.argtypes = [C.c_void_p]
+    lib.sp2_last_error.restype = C.c_char_p
+    lib.sp2_last_error.argtypes = [C.c_void_p]
+    lib.sp2_gershgorin.restype = C.c_int
+    lib.sp2_gershgorin.argtypes = [C.c_void_p, P(sp2_bsr), P(C.c_double), P(C.c_double)]
+    lib.sp2_density.restype = C.c_int
+    lib.sp2_density.argtypes = [C.c_void_p, P(sp2_bsr), C.c_int64, C.c_double, C.c_double, P(C.c_double),
+                                P(C.c_double), P(sp2_options), P(P(sp2_bsr)), P(C.c_double), P(C.c_double),
+                                P(sp2_stats), P(C.c_void_p)]
+    for name in ("sp2_vjp", "sp2_jvp", "sp2_replay"):
+        f = getattr(lib, name)
+        f.restype = C.c_int
+        f.argtypes = [C.c_void_p, C.c_void_p, P(sp2_bsr), P(P(sp2_bsr))]
+    lib.sp2_tape_info.restype = C.c_int
+    lib.sp2_tape_info.argtypes = [C.c_void_p, P(C.c_int32), P(C.c_int32), P(C.c_int64)]
+    lib.sp2_square_step.restype = C.c_int
+    lib.sp2_square_step.argtypes = [C.c_void_p, P(sp2_bsr), C.c_double, C.c_double, C.c_double, C.c_int,
+                                    P(P(sp2_bsr)), P(C.c_double)]
+    lib.sp2_truncate.restype = C.c_int
+    lib.sp2_truncate.argtypes = [C.c_void_p, P(sp2_bsr), C.c_double, C.c_int, C.c_int64, P(P(sp2_bsr)),
+                                 P(C.c_double)]
+    lib.sp2_bsr_copy.restype = C.c_int
+    lib.sp2_bsr_copy.argtypes = [C.c_void_p, P(sp2_bsr), C.c_void_p, C.c_void_p, C.c_void_p]
+    lib.sp2_bsr_free.restype = None
+    lib.sp2_bsr_free.argtypes = [C.c_void_p, P(sp2_bsr)]
+    lib.sp2_tape_free.restype = None
+    lib.sp2_tape_free.argtypes = [C.c_void_p, C.c_void_p]
+    _lib = lib
+    return lib

@@ -1,0 +1,211 @@
+// Internal declarations of the SP2 density-matrix library (gfx950).
+//
+// Device data layout
+// ------------------
+// A symmetric block-sparse matrix is held as
+//   * a pattern: upper-triangle block rows (row_ptr int64[nbr+1], col_idx
+//     int32[nnzb] sorted, row_of int32[nnzb]) plus slot int32[nnzb], the
+//     position of each block in a value pool;
+//   * a value pool: nslots blocks of 64 x 64 row-major values, double or
+//     float.  Truncation only rewrites the pattern: surviving blocks keep their
+//     slot, so values are never copied between iterations.
+// Derived per pattern (Maps):
+//   * idxmap int32[nbr * nbr]: slot of block (min(I,K), max(I,K)) or -1, so
+//     both X_IK and its transpose are found in O(1);
+//   * bits uint32[nbr * W], W = ceil(nbr / 32): row I has bit K set when X_IK
+//     is stored (either orientation);
+//   * adjacency (adj_ptr, adj_col): the set bits of every row, in order.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "sp2dm.h"
+
+namespace sp2 {
+
+constexpr int B = 64;          // block size
+constexpr int BB = B * B;      // elements per block
+constexpr int MAX_NBR = 32768; // dense block maps are nbr^2 int32
+
+struct Exc {
+  int code;
+  std::string msg;
+};
+[[noreturn]] inline void fail(int code, const std::string &msg) { throw Exc{code, msg}; }
+
+#define SP2_HIP(x)                                                                      \
+  do {                                                                                  \
+    hipError_t e_ = (x);                                                                \
+    if (e_ != hipSuccess)                                                               \
+      ::sp2::fail(e_ == hipErrorOutOfMemory ? SP2_ERR_OOM : SP2_ERR_HIP,                \
+                  std::string(#x) + ": " + hipGetErrorString(e_));                      \
+  } while (0)
+
+#define SP2_LAUNCH_CHECK() SP2_HIP(hipGetLastError())
+
+enum Prec : int { P64 = 0, P32 = 1 };  // storage precision of a value pool
+enum Mode : int { M_F64 = 0, M_F32 = 1, M_BF16X3 = 2 };  // arithmetic of a square
+
+struct Ctx;
+
+// ---------------------------------------------------------------- buffers
+struct Buf {
+  Ctx *ctx = nullptr;
+  void *p = nullptr;
+  size_t bytes = 0;
+  Buf() = default;
+  Buf(const Buf &) = delete;
+  Buf &operator=(const Buf &) = delete;
+  Buf(Buf &&o) noexcept { *this = std::move(o); }
+  Buf &operator=(Buf &&o) noexcept;
+  ~Buf() { reset(); }
+  void reset();
+  template <typename T> T *as() const { return static_cast<T *>(p); }
+};
+
+struct Ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  sp2_alloc_fn ualloc = nullptr;
+  sp2_free_fn ufree = nullptr;
+  void *uuser = nullptr;
+  std::string last_error;
+  std::multimap<size_t, void *> cache;  // released buffers, reused by size
+  size_t cached_bytes = 0;
+  size_t live_bytes = 0, peak_bytes = 0;
+  double *h_pinned = nullptr;  // pinned host staging for small device->host reads
+  size_t h_pinned_bytes = 0;
+
+  Buf alloc(size_t bytes);
+  void release(void *p, size_t bytes);
+  void trim();
+  void sync();
+  // small device -> host copy through pinned staging, then stream sync
+  void d2h(void *dst, const void *src, size_t bytes);
+  void h2d(void *dst, const void *src, size_t bytes);
+  void *raw_alloc(size_t bytes);
+  void raw_free(void *p);
+};
+
+// ---------------------------------------------------------------- matrices
+struct Pattern {
+  int64_t n = 0;
+  int nbr = 0;
+  int64_t nnzb = 0;
+  Buf row_ptr;  // int64[nbr+1]
+  Buf col_idx;  // int32[nnzb]
+  Buf row_of;   // int32[nnzb]
+  Buf slot;     // int32[nnzb]
+};
+
+struct Maps {
+  int nbr = 0, W = 0;
+  Buf idxmap;   // int32[nbr*nbr]
+  Buf bits;     // uint32[nbr*W]
+  Buf adj_ptr;  // int64[nbr+1]
+  Buf adj_col;  // int32[adj_ptr[nbr]]
+  int64_t nadj = 0;
+};
+
+struct Pool {
+  Buf vals;
+  int prec = P64;
+  int64_t nslots = 0;
+  std::shared_ptr<Buf> keep;  // shared ownership when a tape also holds it
+};
+
+struct DMat {
+  Pattern pat;
+  std::shared_ptr<Pool> pool;
+};
+
+// ---------------------------------------------------------------- launchers
+// pattern / maps (kernels_pattern.hip)
+void launch_fill_i32(Ctx &c, int32_t *p, int64_t n, int32_t v);
+void launch_fill_u32(Ctx &c, uint32_t *p, int64_t n, uint32_t v);
+void launch_fill_f64(Ctx &c, double *p, int64_t n, double v);
+void launch_iota_i32(Ctx &c, int32_t *p, int64_t n);
+void launch_row_of(Ctx &c, const int64_t *row_ptr, int nbr, int32_t *row_of);
+void launch_validate_pattern(Ctx &c, const int64_t *row_ptr, const int32_t *col_idx, int nbr, int64_t nnzb,
+                             int32_t *flag);
+void launch_build_maps(Ctx &c, const int32_t *row_of, const int32_t *col_idx, const int32_t *slot, int64_t nnzb,
+                       int nbr, int W, int32_t *idxmap, uint32_t *bits);
+void launch_popcount_rows(Ctx &c, const uint32_t *bits, int nbr, int W, int64_t *counts);
+void launch_extract_rows(Ctx &c, const uint32_t *bits, int nbr, int W, const int64_t *ptr, int32_t *cols,
+                         int32_t *rows);
+void launch_symbolic(Ctx &c, const uint32_t *bits, const int64_t *adj_ptr, const int32_t *adj_col, int nbr, int W,
+                     uint32_t *outbits);
+// exclusive scan of n int64 counts into out[0..n] (out[n] = total)
+void scan_exclusive_i64(Ctx &c, const int64_t *in, int64_t *out, int64_t n);
+void launch_diag_missing(Ctx &c, const int64_t *row_ptr, const int32_t *col_idx, int nbr, int64_t *counts);
+void launch_x0_pattern(Ctx &c, const int64_t *frow_ptr, const int32_t *fcol, int nbr, const int64_t *xrow_ptr,
+                       int32_t *xcol, int32_t *src);
+void launch_init_x0(Ctx &c, const double *fval, const int32_t *src, const int32_t *xrow_of, const int32_t *xcol,
+                    int64_t nnzb, int64_t n, double lmax, double w, double *xval);
+
+// values (kernels_values.hip)
+void launch_check_finite(Ctx &c, const double *v, int64_t n, int32_t *flag);
+void launch_gershgorin(Ctx &c, const int32_t *idxmap, const int64_t *adj_ptr, const int32_t *adj_col,
+                       const double *val, int nbr, int64_t n, double *row_lo, double *row_hi);
+void launch_minmax(Ctx &c, const double *lo, const double *hi, int n, double *out2);
+void launch_gather(Ctx &c, const void *src, int src_prec, const int32_t *slot, int64_t nblocks, void *dst,
+                   int dst_prec);
+void launch_reduce_parts(Ctx &c, const double *parts, int64_t nrows, int ncols, double *out);
+void launch_block_norms(Ctx &c, const void *pool, int prec, const int32_t *slot, int64_t nblocks, double *nrm2);
+void launch_update(Ctx &c, const void *xpool, int xprec, const int32_t *xidxmap, int nbr, const int32_t *out_row,
+                   const int32_t *out_col, int64_t nout, void *spool, int sprec, double ca, double cb, double cc,
+                   int64_t n, double *parts);
+
+// squares (kernels_square.hip)
+struct SquareArgs {
+  const void *xpool;
+  int xprec;
+  const int32_t *idxmap;
+  const uint32_t *bits;
+  int nbr, W;
+  const int32_t *out_row, *out_col;
+  int64_t nout;
+  void *opool;
+  int oprec;
+  double ca, cb, cc;
+  int64_t n;
+  double *parts;  // nout x NPART
+};
+constexpr int NPART = 5;  // e2 (weighted), trX, trS, ||out||^2, #K
+void launch_square(Ctx &c, int mode, const SquareArgs &a);
+
+// anticommutator products for the adjoint (kernels_square.hip)
+struct AntiArgs {
+  const double *gpool;      // G values (FP64)
+  const int32_t *gidxmap;
+  const uint32_t *gbits;
+  const double *xpool;      // X values (FP64)
+  const int32_t *xidxmap;
+  const uint32_t *xbits;
+  int nbr, W;
+  const int32_t *out_row, *out_col;
+  int64_t nout;
+  double *opool;            // out = cb * G + cc * (G X + X G), slot = work index
+  double cb, cc;
+};
+void launch_anticommutator(Ctx &c, const AntiArgs &a);
+
+// truncation (kernels_trunc.hip)
+struct TruncOut {
+  std::vector<double> seg_err;  // per segment removed weighted sum
+  int64_t removed = 0;
+};
+// keep[b] (int64, 1 = kept) for every stored block; per-segment removed sums
+void truncate_select(Ctx &c, const Pattern &pat, const double *nrm2_by_block, double tau, int norm,
+                     int64_t coarse_bs, int64_t *keep, TruncOut &out, int nc_out[1]);
+void compact_pattern(Ctx &c, const Pattern &in, const int64_t *keep, Pattern &out);
+void launch_mark_in_mask(Ctx &c, const Pattern &pat, const uint32_t *mask_bits, int W, int64_t *keep);
+
+}  // namespace sp2

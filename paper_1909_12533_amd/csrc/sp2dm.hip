@@ -1,0 +1,1026 @@
+// C ABI and driver of the SP2 / SP2ACC density-matrix expansion.
+//
+// sp2_density follows section "Density matrix construction":
+//   Step 1   schedule (host, schedule.h) and X_0 = (lmax I - F) / w with its
+//            truncation (Algorithm 1);
+//   Step 2   Algorithm 2: per iteration one block-sparse symmetric square of
+//            X~_i on MFMA whose epilogue writes X_{i+1} = f_{i+1}(X~_i) and
+//            the partial sums of e_i = ||X~_i - X~_i^2||_F and
+//            t_i = tr(X~_i - X~_i^2); then the truncation of X_{i+1}; the
+//            parameterless stopping test runs on the host on three scalars;
+//   Step 3   homo/lumo estimates from e_i and t_i (host).
+// The only device -> host traffic per iteration is a handful of scalars and
+// the sizes needed to allocate the next pattern.
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <limits>
+
+#include "internal.h"
+#include "schedule.h"
+
+struct sp2_ctx : public sp2::Ctx {};
+
+namespace sp2 {
+
+namespace {
+
+constexpr double NaN = std::numeric_limits<double>::quiet_NaN();
+
+Buf view(const void *p, size_t bytes) {
+  Buf b;
+  b.p = const_cast<void *>(p);
+  b.bytes = bytes;
+  b.ctx = nullptr;  // not owned
+  return b;
+}
+
+int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
+
+// ------------------------------------------------------------------ matrices
+struct OwnedBsr {
+  sp2_bsr pub;
+  Buf row_ptr, col_idx, val;
+};
+
+void check_input(const sp2_bsr *M, const char *what) {
+  if (!M) fail(SP2_ERR_INVALID_ARG, std::string(what) + " is NULL");
+  if (M->bs != B) fail(SP2_ERR_INVALID_ARG, std::string(what) + ": block size must be 64");
+  if (M->n <= 0) fail(SP2_ERR_INVALID_ARG, std::string(what) + ": n must be positive");
+  if (M->nbr != ceil_div(M->n, B)) fail(SP2_ERR_INVALID_ARG, std::string(what) + ": nbr != ceil(n / 64)");
+  if (M->nbr > MAX_NBR) fail(SP2_ERR_INVALID_ARG, std::string(what) + ": more than 32768 block rows");
+  if (M->nnzb < 0 || M->nnzb > (int64_t)0x7fffffff) fail(SP2_ERR_INVALID_ARG, std::string(what) + ": bad nnzb");
+  if (!M->row_ptr || (M->nnzb > 0 && (!M->col_idx || !M->val)))
+    fail(SP2_ERR_INVALID_ARG, std::string(what) + ": NULL array");
+}
+
+// Borrowed upper BSR -> internal pattern (row_of computed, slot = identity).
+// Validates the structure on the device.
+Pattern borrow_pattern(Ctx &c, const sp2_bsr *M, const char *what) {
+  check_input(M, what);
+  Pattern p;
+  p.n = M->n;
+  p.nbr = (int)M->nbr;
+  p.nnzb = M->nnzb;
+  std::vector<int64_t> rp(p.nbr + 1);
+  c.d2h(rp.data(), M->row_ptr, sizeof(int64_t) * (p.nbr + 1));
+  if (rp[0] != 0 || rp[p.nbr] != p.nnzb) fail(SP2_ERR_INVALID_ARG, std::string(what) + ": row_ptr ends");
+  for (int i = 0; i < p.nbr; ++i)
+    if (rp[i + 1] < rp[i]) fail(SP2_ERR_INVALID_ARG, std::string(what) + ": row_ptr not monotone");
+  p.row_ptr = view(M->row_ptr, sizeof(int64_t) * (p.nbr + 1));
+  p.col_idx = view(M->col_idx, sizeof(int32_t) * p.nnzb);
+  p.row_of = c.alloc(sizeof(int32_t) * (p.nnzb > 0 ? p.nnzb : 1));
+  launch_row_of(c, M->row_ptr, p.nbr, p.row_of.as<int32_t>());
+  Buf flag = c.alloc(sizeof(int32_t));
+  launch_fill_i32(c, flag.as<int32_t>(), 1, 0);
+  launch_validate_pattern(c, M->row_ptr, M->col_idx, p.nbr, p.nnzb, flag.as<int32_t>());
+  int32_t f = 0;
+  c.d2h(&f, flag.p, sizeof(f));
+  if (f) fail(SP2_ERR_INVALID_ARG, std::string(what) + ": columns must satisfy row <= col < nbr, strictly increasing");
+  return p;
+}
+
+void check_finite(Ctx &c, const double *v, int64_t n, const char *what) {
+  Buf flag = c.alloc(sizeof(int32_t));
+  launch_fill_i32(c, flag.as<int32_t>(), 1, 0);
+  launch_check_finite(c, v, n, flag.as<int32_t>());
+  int32_t f = 0;
+  c.d2h(&f, flag.p, sizeof(f));
+  if (f) fail(SP2_ERR_NONFINITE, std::string(what) + " holds non-finite values");
+}
+
+Maps build_maps(Ctx &c, const Pattern &p, bool with_adj) {
+  Maps m;
+  m.nbr = p.nbr;
+  m.W = (p.nbr + 31) / 32;
+  m.idxmap = c.alloc(sizeof(int32_t) * (size_t)p.nbr * p.nbr);
+  m.bits = c.alloc(sizeof(uint32_t) * (size_t)p.nbr * m.W);
+  launch_build_maps(c, p.row_of.as<int32_t>(), p.col_idx.as<int32_t>(), p.slot.p ? p.slot.as<int32_t>() : nullptr,
+                    p.nnzb, p.nbr, m.W, m.idxmap.as<int32_t>(), m.bits.as<uint32_t>());
+  if (with_adj) {
+    Buf cnt = c.alloc(sizeof(int64_t) * p.nbr);
+    m.adj_ptr = c.alloc(sizeof(int64_t) * (p.nbr + 1));
+    launch_popcount_rows(c, m.bits.as<uint32_t>(), p.nbr, m.W, cnt.as<int64_t>());
+    scan_exclusive_i64(c, cnt.as<int64_t>(), m.adj_ptr.as<int64_t>(), p.nbr);
+    c.d2h(&m.nadj, m.adj_ptr.as<int64_t>() + p.nbr, sizeof(int64_t));
+    m.adj_col = c.alloc(sizeof(int32_t) * (m.nadj > 0 ? m.nadj : 1));
+    launch_extract_rows(c, m.bits.as<uint32_t>(), p.nbr, m.W, m.adj_ptr.as<int64_t>(), m.adj_col.as<int32_t>(),
+                        nullptr);
+  }
+  return m;
+}
+
+// block pattern of X^2 (upper blocks), output slot = position
+Pattern symbolic_square(Ctx &c, const Pattern &p, const Maps &m) {
+  Buf outbits = c.alloc(sizeof(uint32_t) * (size_t)p.nbr * m.W);
+  launch_symbolic(c, m.bits.as<uint32_t>(), m.adj_ptr.as<int64_t>(), m.adj_col.as<int32_t>(), p.nbr, m.W,
+                  outbits.as<uint32_t>());
+  Pattern o;
+  o.n = p.n;
+  o.nbr = p.nbr;
+  Buf cnt = c.alloc(sizeof(int64_t) * p.nbr);
+  launch_popcount_rows(c, outbits.as<uint32_t>(), p.nbr, m.W, cnt.as<int64_t>());
+  o.row_ptr = c.alloc(sizeof(int64_t) * (p.nbr + 1));
+  scan_exclusive_i64(c, cnt.as<int64_t>(), o.row_ptr.as<int64_t>(), p.nbr);
+  c.d2h(&o.nnzb, o.row_ptr.as<int64_t>() + p.nbr, sizeof(int64_t));
+  if (o.nnzb > (int64_t)0x7fffffff) fail(SP2_ERR_INVALID_ARG, "square pattern exceeds 2^31 blocks");
+  o.col_idx = c.alloc(sizeof(int32_t) * (o.nnzb > 0 ? o.nnzb : 1));
+  o.row_of = c.alloc(sizeof(int32_t) * (o.nnzb > 0 ? o.nnzb : 1));
+  launch_extract_rows(c, outbits.as<uint32_t>(), p.nbr, m.W, o.row_ptr.as<int64_t>(), o.col_idx.as<int32_t>(),
+                      o.row_of.as<int32_t>());
+  return o;  // slot empty: identity
+}
+
+std::shared_ptr<Pool> new_pool(Ctx &c, int prec, int64_t nslots) {
+  auto pl = std::make_shared<Pool>();
+  pl->prec = prec;
+  pl->nslots = nslots;
+  pl->vals = c.alloc((size_t)(nslots > 0 ? nslots : 1) * BB * (prec == P64 ? 8 : 4));
+  return pl;
+}
+
+const int32_t *slot_ptr(const Pattern &p) { return p.slot.p ? p.slot.as<int32_t>() : nullptr; }
+
+// copy of a pattern (device arrays)
+Pattern clone_pattern(Ctx &c, const Pattern &p) {
+  Pattern o;
+  o.n = p.n;
+  o.nbr = p.nbr;
+  o.nnzb = p.nnzb;
+  const size_t nb = (size_t)(p.nnzb > 0 ? p.nnzb : 1);
+  o.row_ptr = c.alloc(sizeof(int64_t) * (p.nbr + 1));
+  o.col_idx = c.alloc(sizeof(int32_t) * nb);
+  o.row_of = c.alloc(sizeof(int32_t) * nb);
+  SP2_HIP(hipMemcpyAsync(o.row_ptr.p, p.row_ptr.p, sizeof(int64_t) * (p.nbr + 1), hipMemcpyDeviceToDevice, c.stream));
+  if (p.nnzb > 0) {
+    SP2_HIP(hipMemcpyAsync(o.col_idx.p, p.col_idx.p, sizeof(int32_t) * p.nnzb, hipMemcpyDeviceToDevice, c.stream));
+    SP2_HIP(hipMemcpyAsync(o.row_of.p, p.row_of.p, sizeof(int32_t) * p.nnzb, hipMemcpyDeviceToDevice, c.stream));
+  }
+  if (p.slot.p) {
+    o.slot = c.alloc(sizeof(int32_t) * nb);
+    if (p.nnzb > 0)
+      SP2_HIP(hipMemcpyAsync(o.slot.p, p.slot.p, sizeof(int32_t) * p.nnzb, hipMemcpyDeviceToDevice, c.stream));
+  }
+  return o;
+}
+
+// contiguous copy of a matrix in a new pool of precision prec (slot = identity)
+DMat compact_values(Ctx &c, const DMat &m, int prec) {
+  DMat o;
+  o.pat = clone_pattern(c, m.pat);
+  o.pat.slot.reset();
+  o.pool = new_pool(c, prec, m.pat.nnzb);
+  launch_gather(c, m.pool->vals.p, m.pool->prec, slot_ptr(m.pat), m.pat.nnzb, o.pool->vals.p, prec);
+  return o;
+}
+
+sp2_bsr *export_bsr(Ctx &c, const DMat &m) {
+  auto *o = new OwnedBsr();
+  o->row_ptr = c.alloc(sizeof(int64_t) * (m.pat.nbr + 1));
+  o->col_idx = c.alloc(sizeof(int32_t) * (m.pat.nnzb > 0 ? m.pat.nnzb : 1));
+  o->val = c.alloc(sizeof(double) * BB * (size_t)(m.pat.nnzb > 0 ? m.pat.nnzb : 1));
+  SP2_HIP(hipMemcpyAsync(o->row_ptr.p, m.pat.row_ptr.p, sizeof(int64_t) * (m.pat.nbr + 1), hipMemcpyDeviceToDevice,
+                         c.stream));
+  if (m.pat.nnzb > 0)
+    SP2_HIP(hipMemcpyAsync(o->col_idx.p, m.pat.col_idx.p, sizeof(int32_t) * m.pat.nnzb, hipMemcpyDeviceToDevice,
+                           c.stream));
+  launch_gather(c, m.pool->vals.p, m.pool->prec, slot_ptr(m.pat), m.pat.nnzb, o->val.p, P64);
+  c.sync();
+  o->pub.n = m.pat.n;
+  o->pub.bs = B;
+  o->pub.owned = 1;
+  o->pub.nbr = m.pat.nbr;
+  o->pub.nnzb = m.pat.nnzb;
+  o->pub.row_ptr = o->row_ptr.as<int64_t>();
+  o->pub.col_idx = o->col_idx.as<int32_t>();
+  o->pub.val = o->val.as<double>();
+  return &o->pub;
+}
+
+// borrowed input matrix as an internal DMat (values not copied)
+DMat borrow_matrix(Ctx &c, const sp2_bsr *M, const char *what) {
+  DMat d;
+  d.pat = borrow_pattern(c, M, what);
+  d.pool = std::make_shared<Pool>();
+  d.pool->prec = P64;
+  d.pool->nslots = M->nnzb;
+  d.pool->vals = view(M->val, sizeof(double) * BB * (size_t)M->nnzb);
+  return d;
+}
+
+// ------------------------------------------------------------------ steps
+struct SquareOut {
+  DMat next;      // X_{i+1} (or S when fused == false) on the square's pattern
+  Buf parts;      // nout x NPART
+  double sums[NPART];
+  double kernel_s = 0.0;  // device time of the MFMA square (HIP events)
+};
+
+struct EventPair {
+  hipEvent_t a = nullptr, b = nullptr;
+  EventPair() {
+    SP2_HIP(hipEventCreate(&a));
+    SP2_HIP(hipEventCreate(&b));
+  }
+  ~EventPair() {
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+  }
+};
+
+SquareOut square_step(Ctx &c, const DMat &X, const Maps &m, int mode, int oprec, double ca, double cb, double cc) {
+  SquareOut r;
+  r.next.pat = symbolic_square(c, X.pat, m);
+  const int64_t nout = r.next.pat.nnzb;
+  r.next.pool = new_pool(c, oprec, nout);
+  r.parts = c.alloc(sizeof(double) * NPART * (size_t)(nout > 0 ? nout : 1));
+  SquareArgs a;
+  a.xpool = X.pool->vals.p;
+  a.xprec = X.pool->prec;
+  a.idxmap = m.idxmap.as<int32_t>();
+  a.bits = m.bits.as<uint32_t>();
+  a.nbr = X.pat.nbr;
+  a.W = m.W;
+  a.out_row = r.next.pat.row_of.as<int32_t>();
+  a.out_col = r.next.pat.col_idx.as<int32_t>();
+  a.nout = nout;
+  a.opool = r.next.pool->vals.p;
+  a.oprec = oprec;
+  a.ca = ca;
+  a.cb = cb;
+  a.cc = cc;
+  a.n = X.pat.n;
+  a.parts = r.parts.as<double>();
+  EventPair ev;
+  SP2_HIP(hipEventRecord(ev.a, c.stream));
+  launch_square(c, mode, a);
+  SP2_HIP(hipEventRecord(ev.b, c.stream));
+  Buf sums = c.alloc(sizeof(double) * NPART);
+  launch_reduce_parts(c, r.parts.as<double>(), nout, NPART, sums.as<double>());
+  c.d2h(r.sums, sums.p, sizeof(double) * NPART);
+  float ms = 0.0f;
+  SP2_HIP(hipEventElapsedTime(&ms, ev.a, ev.b));
+  r.kernel_s = 1e-3 * (double)ms;
+  return r;
+}
+
+struct TruncResult {
+  double err_frob = 0.0, err_mixed = 0.0;
+  int64_t removed = 0;
+};
+
+// truncate in place (pattern replaced; pool untouched)
+TruncResult truncate_matrix(Ctx &c, DMat &X, const double *nrm2, double tau, int norm, int64_t coarse_bs) {
+  TruncResult res;
+  if (norm == SP2_TRUNC_NONE || !(tau > 0.0)) return res;
+  Buf keep = c.alloc(sizeof(int64_t) * (X.pat.nnzb > 0 ? X.pat.nnzb : 1));
+  TruncOut to;
+  int nc = 1;
+  truncate_select(c, X.pat, nrm2, tau, norm, coarse_bs, keep.as<int64_t>(), to, &nc);
+  res.removed = to.removed;
+  if (to.removed > 0) {
+    Pattern np;
+    if (!X.pat.slot.p) {  // identity slots: materialise before compaction
+      X.pat.slot = c.alloc(sizeof(int32_t) * (X.pat.nnzb > 0 ? X.pat.nnzb : 1));
+      launch_iota_i32(c, X.pat.slot.as<int32_t>(), X.pat.nnzb);
+    }
+    compact_pattern(c, X.pat, keep.as<int64_t>(), np);
+    X.pat = std::move(np);
+  }
+  // error norms of E from the per-segment removed sums
+  if (norm == SP2_TRUNC_FROB) {
+    const double s = to.seg_err.empty() ? 0.0 : to.seg_err[0];
+    res.err_frob = std::sqrt(s);
+    res.err_mixed = res.err_frob;
+  } else if (!to.seg_err.empty()) {
+    double f2 = 0.0, mx = 0.0;
+    for (int R = 0; R < nc; ++R) {
+      double row = 0.0;
+      for (int S = 0; S < nc; ++S) {
+        const double v = (R <= S) ? to.seg_err[(size_t)R * nc + S] : to.seg_err[(size_t)S * nc + R];
+        row += std::sqrt(v);
+        if (R == S)
+          f2 += v;
+        else if (R < S)
+          f2 += 2.0 * v;
+      }
+      mx = std::fmax(mx, row);
+    }
+    res.err_frob = std::sqrt(f2);
+    res.err_mixed = mx;
+  }
+  return res;
+}
+
+Buf column(Ctx &c, const Buf &parts, int64_t nrows, int col);
+
+}  // namespace
+
+}  // namespace sp2
+
+// column extraction kernel (strided partial sums -> contiguous)
+namespace sp2 {
+namespace {
+__global__ void k_col(const double *parts, int64_t nrows, int ncols, int col, double *out) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < nrows) out[i] = parts[i * ncols + col];
+}
+Buf column(Ctx &c, const Buf &parts, int64_t nrows, int col) {
+  Buf o = c.alloc(sizeof(double) * (nrows > 0 ? nrows : 1));
+  if (nrows > 0) {
+    k_col<<<(unsigned)((nrows + 255) / 256), 256, 0, c.stream>>>(parts.as<double>(), nrows, NPART, col,
+                                                                 o.as<double>());
+    SP2_LAUNCH_CHECK();
+  }
+  return o;
+}
+}  // namespace
+}  // namespace sp2
+
+
+// ====================================================================== driver
+namespace sp2 {
+
+namespace {
+
+__global__ void k_scale(double *v, int64_t n, double s) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    v[i] *= s;
+}
+void scale_pool(Ctx &c, double *v, int64_t n, double s) {
+  if (n <= 0) return;
+  int64_t g = (n + 255) / 256;
+  if (g > 65536) g = 65536;
+  k_scale<<<(unsigned)g, 256, 0, c.stream>>>(v, n, s);
+  SP2_LAUNCH_CHECK();
+}
+
+// X_0 = (lmax I - F) / w on F's pattern plus the diagonal blocks (Algorithm 1)
+DMat init_x0(Ctx &c, const DMat &F, double lmax, double w) {
+  const int nbr = F.pat.nbr;
+  Buf cnt = c.alloc(sizeof(int64_t) * nbr);
+  launch_diag_missing(c, F.pat.row_ptr.as<int64_t>(), F.pat.col_idx.as<int32_t>(), nbr, cnt.as<int64_t>());
+  DMat X;
+  X.pat.n = F.pat.n;
+  X.pat.nbr = nbr;
+  X.pat.row_ptr = c.alloc(sizeof(int64_t) * (nbr + 1));
+  scan_exclusive_i64(c, cnt.as<int64_t>(), X.pat.row_ptr.as<int64_t>(), nbr);
+  c.d2h(&X.pat.nnzb, X.pat.row_ptr.as<int64_t>() + nbr, sizeof(int64_t));
+  const int64_t nn = X.pat.nnzb;
+  X.pat.col_idx = c.alloc(sizeof(int32_t) * nn);
+  X.pat.row_of = c.alloc(sizeof(int32_t) * nn);
+  Buf src = c.alloc(sizeof(int32_t) * nn);
+  launch_x0_pattern(c, F.pat.row_ptr.as<int64_t>(), F.pat.col_idx.as<int32_t>(), nbr, X.pat.row_ptr.as<int64_t>(),
+                    X.pat.col_idx.as<int32_t>(), src.as<int32_t>());
+  launch_row_of(c, X.pat.row_ptr.as<int64_t>(), nbr, X.pat.row_of.as<int32_t>());
+  X.pool = new_pool(c, P64, nn);
+  launch_init_x0(c, F.pool->vals.as<double>(), src.as<int32_t>(), X.pat.row_of.as<int32_t>(),
+                 X.pat.col_idx.as<int32_t>(), nn, F.pat.n, lmax, w, X.pool->vals.as<double>());
+  return X;
+}
+
+Buf norms_of(Ctx &c, const DMat &X) {
+  Buf nrm2 = c.alloc(sizeof(double) * (X.pat.nnzb > 0 ? X.pat.nnzb : 1));
+  launch_block_norms(c, X.pool->vals.p, X.pool->prec, slot_ptr(X.pat), X.pat.nnzb, nrm2.as<double>());
+  return nrm2;
+}
+
+// restrict X to the blocks present in mask (pattern + slots rewritten)
+void restrict_to(Ctx &c, DMat &X, const Pattern &mask) {
+  Maps mm = build_maps(c, mask, false);
+  Buf keep = c.alloc(sizeof(int64_t) * (X.pat.nnzb > 0 ? X.pat.nnzb : 1));
+  launch_mark_in_mask(c, X.pat, mm.bits.as<uint32_t>(), mm.W, keep.as<int64_t>());
+  if (!X.pat.slot.p) {
+    X.pat.slot = c.alloc(sizeof(int32_t) * (X.pat.nnzb > 0 ? X.pat.nnzb : 1));
+    launch_iota_i32(c, X.pat.slot.as<int32_t>(), X.pat.nnzb);
+  }
+  Pattern np;
+  compact_pattern(c, X.pat, keep.as<int64_t>(), np);
+  X.pat = std::move(np);
+}
+
+// low-precision square cannot resolve e below ~ unit roundoff * ||X||_F
+double low_floor(int mode, double trX) {
+  const double u = (mode == M_BF16X3) ? 1.0 / 65536.0 : 1.0 / 16777216.0;
+  return 8.0 * u * std::sqrt(std::fmax(trX, 1.0));
+}
+
+}  // namespace
+
+struct TapeIter {
+  Pattern mask;                  // block pattern of X~_i
+  int p = -1;                    // polynomial that produced X_i (i >= 1)
+  double alpha = 1.0, ca = 0.0, cb = 0.0, cc = 0.0;
+  int mode = M_F64;              // arithmetic of the square of X~_i
+  int prec = P64;                // storage precision of X~_i
+  std::shared_ptr<DMat> ckpt;    // compact copy of X~_i, or empty
+};
+
+struct Tape {
+  Ctx *ctx = nullptr;
+  int64_t n = 0, n_occ = 0;
+  double lmax = 0.0, w = 1.0;
+  int n_iter = 0, n_ckpt = 0;
+  int64_t bytes = 0;
+  std::vector<TapeIter> it;
+};
+
+}  // namespace sp2
+
+struct sp2_tape : public sp2::Tape {};
+
+namespace sp2 {
+namespace {
+
+void add_checkpoint(Ctx &c, Tape &t, int i, const DMat &X) {
+  auto d = std::make_shared<DMat>(compact_values(c, X, X.pool->prec));
+  t.bytes += (int64_t)d->pat.nnzb * BB * (d->pool->prec == P64 ? 8 : 4);
+  t.it[i].ckpt = d;
+  t.n_ckpt++;
+}
+
+int run_density(Ctx &c, const sp2_bsr *Fin, int64_t n_occ, double lmin, double lmax, const double *hub,
+                const double *llb, const sp2_options &o, sp2_bsr **D_out, double *hest, double *lest,
+                sp2_stats *st, sp2_tape **tape_out) {
+  // ---- argument checks ---------------------------------------------------------
+  if (!D_out) fail(SP2_ERR_INVALID_ARG, "D_out is NULL");
+  *D_out = nullptr;
+  if (tape_out) *tape_out = nullptr;
+  check_input(Fin, "F");
+  const int64_t N = Fin->n;
+  if (!(n_occ > 0 && n_occ < N)) fail(SP2_ERR_INVALID_ARG, "n_occ must lie in (0, n)");
+  if (!(std::isfinite(lmin) && std::isfinite(lmax) && lmin < lmax))
+    fail(SP2_ERR_INVALID_ARG, "need finite lmin < lmax");
+  if ((hub == nullptr) != (llb == nullptr)) fail(SP2_ERR_INVALID_ARG, "give both homo/lumo bounds or neither");
+  if (hub && !(lmin <= *hub && *hub < *llb && *llb <= lmax))
+    fail(SP2_ERR_BAD_BOUNDS, "bounds must satisfy lmin <= homo_ub < lumo_lb <= lmax");
+  if (o.precision < 0 || o.precision > 2) fail(SP2_ERR_INVALID_ARG, "unknown precision");
+  if (o.trunc_norm < 0 || o.trunc_norm > 2) fail(SP2_ERR_INVALID_ARG, "unknown truncation norm");
+  if (o.n_max_cap < 1 || o.n_max_cap > 1000) fail(SP2_ERR_INVALID_ARG, "n_max_cap must be in [1, 1000]");
+  if (o.trunc_norm == SP2_TRUNC_FROBINF && (o.coarse_bs <= 0 || o.coarse_bs % B))
+    fail(SP2_ERR_INVALID_ARG, "coarse_bs must be a positive multiple of 64");
+  if (!(o.gamma >= 0.0) || !(o.tau_fixed >= 0.0) || !(o.switch_tol >= 0.0) || !(o.idem_stop >= 0.0))
+    fail(SP2_ERR_INVALID_ARG, "tolerances must be >= 0");
+  if (st && st->capacity < o.n_max_cap + 1) fail(SP2_ERR_INVALID_ARG, "stats capacity < n_max_cap + 1");
+  if (tape_out && !o.record_tape) fail(SP2_ERR_INVALID_ARG, "a tape needs record_tape = 1");
+  const int lowmode = o.precision == SP2_PREC_FP32 ? M_F32 : (o.precision == SP2_PREC_BF16X3 ? M_BF16X3 : M_F64);
+
+  auto t_start = std::chrono::steady_clock::now();
+  DMat F = borrow_matrix(c, Fin, "F");
+  check_finite(c, Fin->val, Fin->nnzb * (int64_t)BB, "F");
+
+  // ---- Step 1 ---------------------------------------------------------------------
+  const double w = lmax - lmin;
+  Sched sch = hub ? make_schedule(lmin, lmax, *hub, *llb, o.accel != 0, o.gamma, o.tau_fixed, o.n_max_cap)
+                  : make_tc2(lmin, lmax, o.tau_fixed, o.n_max_cap);
+  const int n_max = sch.n_max;
+
+  std::unique_ptr<sp2_tape> tape;
+  int ck_every = 1;
+  if (o.record_tape) {
+    tape.reset(new sp2_tape());
+    tape->ctx = &c;
+    tape->n = N;
+    tape->n_occ = n_occ;
+    tape->lmax = lmax;
+    tape->w = w;
+    const int nck = o.n_checkpoints > 0 ? o.n_checkpoints : (int)std::ceil(std::sqrt((double)(n_max + 1)));
+    ck_every = std::max(1, (int)std::ceil((double)(n_max + 1) / (double)nck));
+  }
+
+  // ---- Algorithm 1 ------------------------------------------------------------------
+  DMat X = init_x0(c, F, lmax, w);
+  std::vector<double> e, t, trv, errF, errM, itime, iflops, ksq, alph{1.0}, taus;
+  std::vector<int> p{-1}, precv;
+  std::vector<int64_t> nnzbv;
+  {
+    Buf nrm2 = norms_of(c, X);
+    TruncResult tr = truncate_matrix(c, X, nrm2.as<double>(), sch.tau[0], o.trunc_norm, o.coarse_bs);
+    errF.push_back(tr.err_frob);
+    errM.push_back(tr.err_mixed);
+    taus.push_back(sch.tau[0]);
+  }
+  if (lowmode != M_F64) X = compact_values(c, X, P32);
+  int switch_iter = lowmode != M_F64 ? -1 : 0;
+
+  int n = -1, stop_reason = 0, status = SP2_OK;
+  double alg_flops = 0.0;
+  int64_t max_nnzb = 0;
+  for (int i = 0;; ++i) {
+    auto t_it = std::chrono::steady_clock::now();
+    const int mode = X.pool->prec == P32 ? lowmode : M_F64;
+    if (tape) {
+      tape->it.emplace_back();
+      TapeIter &ti = tape->it.back();
+      ti.mask = clone_pattern(c, X.pat);
+      ti.mask.slot.reset();
+      ti.mode = mode;
+      ti.prec = X.pool->prec;
+      if (i >= 1) {
+        ti.p = p[i];
+        ti.alpha = alph[i];
+        poly_coeffs(p[i], alph[i], ti.ca, ti.cb, ti.cc);
+      }
+      if (i % ck_every == 0) add_checkpoint(c, *tape, i, X);
+    }
+    nnzbv.push_back(X.pat.nnzb);
+    max_nnzb = std::max(max_nnzb, X.pat.nnzb);
+    precv.push_back(mode == M_F64 ? SP2_PREC_FP64 : o.precision);
+
+    Maps m = build_maps(c, X.pat, true);
+    const bool have_next = i < n_max;
+    double ca = 0.0, cb = 0.0, cc = 1.0;
+    if (sch.bounds && have_next) poly_coeffs(sch.p[i + 1], sch.alpha[i + 1], ca, cb, cc);
+    SquareOut so = square_step(c, X, m, mode, X.pool->prec, ca, cb, cc);
+    const double ei = std::sqrt(std::fmax(so.sums[0], 0.0));
+    const double trX = so.sums[1], trS = so.sums[2];
+    e.push_back(ei);
+    t.push_back(trX - trS);
+    trv.push_back(trX);
+    const double fl = so.sums[4] * 2.0 * B * B * B;
+    iflops.push_back(fl);
+    ksq.push_back(so.kernel_s);
+    alg_flops += fl;
+
+    // ---- stopping test (Algorithm 2) -----------------------------------------
+    // the criterion compares e_i with e_{i-2}: both must come from FP64 squares
+    bool stop = false;
+    const bool fp64_window = mode == M_F64 && (switch_iter >= 0 && i >= switch_iter + 2);
+    if (i >= 1 && fp64_window) {
+      if (i >= std::max(sch.n_min, 2) && p[i] != p[i - 1] && e[i] > C_STOP * e[i - 2] * e[i - 2]) {
+        stop = true;
+        stop_reason = SP2_STOP_CRITERION;
+      } else if (o.idem_stop > 0.0 && e[i] <= o.idem_stop) {
+        stop = true;
+        stop_reason = SP2_STOP_IDEMPOTENCY;
+      }
+    }
+    if (!stop && i == n_max) {
+      stop = true;
+      stop_reason = SP2_STOP_NMAX;
+      status = SP2_WARN_NOT_CONVERGED;
+    }
+    if (stop) {
+      n = i;
+      c.sync();
+      itime.push_back(std::chrono::duration<double>(std::chrono::steady_clock::now() - t_it).count());
+      break;
+    }
+
+    // ---- next polynomial and truncation of X_{i+1} ----------------------------------
+    int pn;
+    double an;
+    if (sch.bounds) {
+      pn = sch.p[i + 1];
+      an = sch.alpha[i + 1];
+    } else {
+      pn = std::fabs(trS - (double)n_occ) < std::fabs(2.0 * trX - trS - (double)n_occ) ? 1 : 0;
+      an = 1.0;
+      poly_coeffs(pn, an, ca, cb, cc);
+      launch_update(c, X.pool->vals.p, X.pool->prec, m.idxmap.as<int32_t>(), X.pat.nbr,
+                    so.next.pat.row_of.as<int32_t>(), so.next.pat.col_idx.as<int32_t>(), so.next.pat.nnzb,
+                    so.next.pool->vals.p, so.next.pool->prec, ca, cb, cc, N, so.parts.as<double>());
+    }
+    p.push_back(pn);
+    alph.push_back(an);
+    DMat Xn = std::move(so.next);
+    const int64_t nout = Xn.pat.nnzb;
+    {
+      Buf nrm2 = column(c, so.parts, nout, 3);
+      TruncResult tr = truncate_matrix(c, Xn, nrm2.as<double>(), sch.tau[i + 1], o.trunc_norm, o.coarse_bs);
+      errF.push_back(tr.err_frob);
+      errM.push_back(tr.err_mixed);
+      taus.push_back(sch.tau[i + 1]);
+    }
+    if (Xn.pool->prec == P32 && (ei < o.switch_tol || ei < low_floor(mode, trX))) {
+      Xn = compact_values(c, Xn, P64);
+      switch_iter = i + 1;
+    }
+    X = std::move(Xn);
+    c.sync();
+    itime.push_back(std::chrono::duration<double>(std::chrono::steady_clock::now() - t_it).count());
+  }
+
+  // ---- Step 3 and outputs ---------------------------------------------------------
+  double h = NaN, l = NaN;
+  homo_lumo(sch, e, trv, p, alph, n, lmin, lmax, N, n_occ, h, l);
+  double bound = NaN;
+  if (sch.bounds) {
+    bound = 0.0;
+    for (int i = 0; i <= n; ++i)
+      if (errM[i] > 0.0) bound += errM[i] / (sch.xi[i] - errM[i]);
+  }
+  if (status == SP2_OK && std::fabs(trv[n] - (double)n_occ) > 0.5) status = SP2_WARN_TRACE;
+  *D_out = export_bsr(c, X);
+  const double elapsed = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+  if (hest) *hest = h;
+  if (lest) *lest = l;
+  if (st) {
+    st->n_iter = n;
+    st->n_max = n_max;
+    st->n_min = sch.n_min;
+    st->stop_reason = stop_reason;
+    st->switch_iter = switch_iter;
+    st->homo_ub_est = h;
+    st->lumo_lb_est = l;
+    st->subspace_err_bound = bound;
+    st->time_s = elapsed;
+    st->alg_flops = alg_flops;
+    st->max_nnzb = max_nnzb;
+    st->square_time_total_s = 0.0;
+    for (int i = 0; i <= n; ++i) st->square_time_total_s += ksq[i];
+    for (int i = 0; i <= n; ++i) {
+      if (st->square_time_s) st->square_time_s[i] = ksq[i];
+      if (st->e) st->e[i] = e[i];
+      if (st->t) st->t[i] = t[i];
+      if (st->trace) st->trace[i] = trv[i];
+      if (st->alpha) st->alpha[i] = alph[i];
+      if (st->tau) st->tau[i] = taus[i];
+      if (st->trunc_err_frob) st->trunc_err_frob[i] = errF[i];
+      if (st->trunc_err_mixed) st->trunc_err_mixed[i] = errM[i];
+      if (st->iter_time_s) st->iter_time_s[i] = itime[i];
+      if (st->iter_flops) st->iter_flops[i] = iflops[i];
+      if (st->p) st->p[i] = p[i];
+      if (st->precision) st->precision[i] = precv[i];
+      if (st->nnzb) st->nnzb[i] = nnzbv[i];
+    }
+  }
+  if (tape) {
+    tape->n_iter = n;
+    tape->it.resize(n + 1);
+    *tape_out = tape.release();
+  }
+  return status;
+}
+
+// ---------------------------------------------------------------- adjoint
+// X~_{i} from X~_{i-1} with the recorded polynomial and mask (frozen map)
+DMat replay_step(Ctx &c, const Tape &t, int i, const DMat &Xprev) {
+  const TapeIter &ti = t.it[i];
+  const TapeIter &tp = t.it[i - 1];
+  Maps m = build_maps(c, Xprev.pat, true);
+  SquareOut so = square_step(c, Xprev, m, tp.mode, Xprev.pool->prec, ti.ca, ti.cb, ti.cc);
+  DMat Xn = std::move(so.next);
+  restrict_to(c, Xn, ti.mask);
+  if (Xn.pool->prec != ti.prec) Xn = compact_values(c, Xn, ti.prec);
+  return Xn;
+}
+
+DMat checkpoint_copy(const Tape &t, int i) {
+  DMat d;
+  const DMat &ck = *t.it[i].ckpt;
+  Ctx &c = *t.ctx;
+  d.pat = clone_pattern(c, ck.pat);
+  d.pool = ck.pool;  // shared, read-only
+  return d;
+}
+
+DMat as_f64(Ctx &c, const DMat &X) {
+  if (X.pool->prec == P64) {
+    DMat d;
+    d.pat = clone_pattern(c, X.pat);
+    d.pool = X.pool;
+    return d;
+  }
+  return compact_values(c, X, P64);
+}
+
+// out = cb G + cc (G X + X G) on the pattern outpat
+DMat anticommutator(Ctx &c, const DMat &G, const DMat &X, const Pattern &outpat, double cb, double cc) {
+  Maps mg = build_maps(c, G.pat, false), mx = build_maps(c, X.pat, false);
+  DMat o;
+  o.pat = clone_pattern(c, outpat);
+  o.pat.slot.reset();
+  o.pool = new_pool(c, P64, o.pat.nnzb);
+  AntiArgs a;
+  a.gpool = G.pool->vals.as<double>();
+  a.gidxmap = mg.idxmap.as<int32_t>();
+  a.gbits = mg.bits.as<uint32_t>();
+  a.xpool = X.pool->vals.as<double>();
+  a.xidxmap = mx.idxmap.as<int32_t>();
+  a.xbits = mx.bits.as<uint32_t>();
+  a.nbr = G.pat.nbr;
+  a.W = mg.W;
+  a.out_row = o.pat.row_of.as<int32_t>();
+  a.out_col = o.pat.col_idx.as<int32_t>();
+  a.nout = o.pat.nnzb;
+  a.opool = o.pool->vals.as<double>();
+  a.cb = cb;
+  a.cc = cc;
+  launch_anticommutator(c, a);
+  return o;
+}
+
+int last_ckpt_at_or_below(const Tape &t, int i) {
+  for (int k = i; k >= 0; --k)
+    if (t.it[k].ckpt) return k;
+  fail(SP2_ERR_INVALID_ARG, "tape has no checkpoint");
+}
+
+void check_same_n(const Tape &t, const sp2_bsr *M, const char *what) {
+  check_input(M, what);
+  if (M->n != t.n) fail(SP2_ERR_INVALID_ARG, std::string(what) + ": dimension differs from the recorded run");
+}
+
+sp2_bsr *run_vjp(Ctx &c, const Tape &t, const sp2_bsr *Win) {
+  check_same_n(t, Win, "W");
+  DMat W = borrow_matrix(c, Win, "W");
+  check_finite(c, Win->val, Win->nnzb * (int64_t)BB, "W");
+  const int n = t.n_iter;
+  DMat Xbar = std::move(W);
+  restrict_to(c, Xbar, t.it[n].mask);  // G_n = M_n o W
+  // segment cache of X~_{k} for k in [seg_lo, seg_hi]
+  std::vector<DMat> seg;
+  int seg_lo = 1, seg_hi = 0;
+  for (int i = n; i >= 1; --i) {
+    if (!(i - 1 >= seg_lo && i - 1 <= seg_hi)) {
+      seg.clear();
+      const int c0 = last_ckpt_at_or_below(t, i - 1);
+      seg.push_back(checkpoint_copy(t, c0));
+      for (int k = c0 + 1; k <= i - 1; ++k) seg.push_back(replay_step(c, t, k, seg.back()));
+      seg_lo = c0;
+      seg_hi = i - 1;
+    }
+    const DMat X = as_f64(c, seg[(i - 1) - seg_lo]);
+    const TapeIter &ti = t.it[i];
+    Xbar = anticommutator(c, Xbar, X, t.it[i - 1].mask, ti.cb, ti.cc);
+    if (i - 1 < seg_hi) seg.resize((i - 1) - seg_lo + 1);  // drop X~ no longer needed
+    seg_hi = i - 1;
+  }
+  // Fbar = -(M_0 o Xbar) / w  (Xbar already lives on M_0)
+  DMat Fb = compact_values(c, Xbar, P64);
+  scale_pool(c, Fb.pool->vals.as<double>(), Fb.pat.nnzb * (int64_t)BB, -1.0 / t.w);
+  return export_bsr(c, Fb);
+}
+
+sp2_bsr *run_jvp(Ctx &c, const Tape &t, const sp2_bsr *dFin) {
+  check_same_n(t, dFin, "dF");
+  DMat dF = borrow_matrix(c, dFin, "dF");
+  check_finite(c, dFin->val, dFin->nnzb * (int64_t)BB, "dF");
+  restrict_to(c, dF, t.it[0].mask);
+  DMat dX = compact_values(c, dF, P64);
+  scale_pool(c, dX.pool->vals.as<double>(), dX.pat.nnzb * (int64_t)BB, -1.0 / t.w);
+  DMat X = checkpoint_copy(t, 0);
+  for (int i = 1; i <= t.n_iter; ++i) {
+    const TapeIter &ti = t.it[i];
+    const DMat X64 = as_f64(c, X);
+    DMat nd = anticommutator(c, dX, X64, ti.mask, ti.cb, ti.cc);
+    dX = std::move(nd);
+    if (i < t.n_iter) X = replay_step(c, t, i, X);
+  }
+  return export_bsr(c, dX);
+}
+
+sp2_bsr *run_replay(Ctx &c, const Tape &t, const sp2_bsr *Fin) {
+  check_same_n(t, Fin, "F");
+  DMat F = borrow_matrix(c, Fin, "F");
+  check_finite(c, Fin->val, Fin->nnzb * (int64_t)BB, "F");
+  DMat X = init_x0(c, F, t.lmax, t.w);
+  restrict_to(c, X, t.it[0].mask);
+  if (t.it[0].prec == P32) X = compact_values(c, X, P32);
+  for (int i = 1; i <= t.n_iter; ++i) X = replay_step(c, t, i, X);
+  return export_bsr(c, X);
+}
+
+template <typename Fn> int guarded(sp2_ctx *ctx, Fn &&fn) {
+  if (!ctx) return SP2_ERR_INVALID_ARG;
+  ctx->last_error.clear();
+  try {
+    SP2_HIP(hipSetDevice(ctx->device));
+    return fn();
+  } catch (const Exc &e) {
+    ctx->last_error = e.msg;
+    (void)hipGetLastError();
+    return e.code;
+  } catch (const std::bad_alloc &) {
+    ctx->last_error = "host allocation failed";
+    return SP2_ERR_OOM;
+  } catch (const std::exception &e) {
+    ctx->last_error = e.what();
+    return SP2_ERR_HIP;
+  }
+}
+
+}  // namespace
+}  // namespace sp2
+
+// ====================================================================== C ABI
+using namespace sp2;
+
+extern "C" {
+
+const char *sp2_version(void) { return "sp2dm 0.1 gfx950"; }
+
+void sp2_options_default(sp2_options *o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->accel = 1;
+  o->precision = SP2_PREC_FP64;
+  o->switch_tol = 1e-3;
+  o->trunc_norm = SP2_TRUNC_FROBINF;
+  o->n_max_cap = 100;
+  o->coarse_bs = 4096;
+  o->gamma = 1e-3;
+  o->tau_fixed = 0.0;
+  o->idem_stop = 0.0;
+  o->record_tape = 0;
+  o->n_checkpoints = 0;
+}
+
+int sp2_create(sp2_ctx **ctx, int device, void *hip_stream) {
+  if (!ctx) return SP2_ERR_INVALID_ARG;
+  *ctx = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) {
+    (void)hipGetLastError();
+    return SP2_ERR_HIP;
+  }
+  if (hipSetDevice(device) != hipSuccess) return SP2_ERR_HIP;
+  auto *c = new sp2_ctx();
+  c->device = device;
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  *ctx = c;
+  return SP2_OK;
+}
+
+void sp2_destroy(sp2_ctx *ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
+  ctx->trim();
+  delete ctx;
+}
+
+int sp2_set_allocator(sp2_ctx *ctx, sp2_alloc_fn alloc, sp2_free_fn free_, void *user) {
+  return guarded(ctx, [&]() {
+    if ((alloc == nullptr) != (free_ == nullptr)) fail(SP2_ERR_INVALID_ARG, "give both alloc and free or neither");
+    ctx->sync();
+    ctx->trim();
+    ctx->ualloc = alloc;
+    ctx->ufree = free_;
+    ctx->uuser = user;
+    return SP2_OK;
+  });
+}
+
+void sp2_trim(sp2_ctx *ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->device);
+  ctx->trim();
+}
+
+const char *sp2_last_error(const sp2_ctx *ctx) { return ctx ? ctx->last_error.c_str() : "NULL context"; }
+
+int sp2_gershgorin(sp2_ctx *ctx, const sp2_bsr *F, double *lmin, double *lmax) {
+  return guarded(ctx, [&]() {
+    if (!lmin || !lmax) fail(SP2_ERR_INVALID_ARG, "NULL output");
+    DMat M = borrow_matrix(*ctx, F, "F");
+    check_finite(*ctx, F->val, F->nnzb * (int64_t)BB, "F");
+    Maps m = build_maps(*ctx, M.pat, true);
+    Buf lo = ctx->alloc(sizeof(double) * M.pat.nbr), hi = ctx->alloc(sizeof(double) * M.pat.nbr);
+    launch_gershgorin(*ctx, m.idxmap.as<int32_t>(), m.adj_ptr.as<int64_t>(), m.adj_col.as<int32_t>(),
+                      M.pool->vals.as<double>(), M.pat.nbr, M.pat.n, lo.as<double>(), hi.as<double>());
+    Buf out = ctx->alloc(2 * sizeof(double));
+    launch_minmax(*ctx, lo.as<double>(), hi.as<double>(), M.pat.nbr, out.as<double>());
+    double h[2];
+    ctx->d2h(h, out.p, sizeof(h));
+    *lmin = h[0];
+    *lmax = h[1];
+    return SP2_OK;
+  });
+}
+
+int sp2_density(sp2_ctx *ctx, const sp2_bsr *F, int64_t n_occ, double lmin, double lmax, const double *homo_ub,
+                const double *lumo_lb, const sp2_options *opt, sp2_bsr **D_out, double *homo_est, double *lumo_est,
+                sp2_stats *stats, sp2_tape **tape) {
+  return guarded(ctx, [&]() {
+    sp2_options o;
+    if (opt)
+      o = *opt;
+    else
+      sp2_options_default(&o);
+    return run_density(*ctx, F, n_occ, lmin, lmax, homo_ub, lumo_lb, o, D_out, homo_est, lumo_est, stats, tape);
+  });
+}
+
+int sp2_vjp(sp2_ctx *ctx, const sp2_tape *tape, const sp2_bsr *W, sp2_bsr **Fbar_out) {
+  return guarded(ctx, [&]() {
+    if (!tape || !Fbar_out) fail(SP2_ERR_INVALID_ARG, "NULL tape or output");
+    *Fbar_out = nullptr;
+    *Fbar_out = run_vjp(*ctx, *tape, W);
+    return SP2_OK;
+  });
+}
+
+int sp2_jvp(sp2_ctx *ctx, const sp2_tape *tape, const sp2_bsr *dF, sp2_bsr **dD_out) {
+  return guarded(ctx, [&]() {
+    if (!tape || !dD_out) fail(SP2_ERR_INVALID_ARG, "NULL tape or output");
+    *dD_out = nullptr;
+    *dD_out = run_jvp(*ctx, *tape, dF);
+    return SP2_OK;
+  });
+}
+
+int sp2_replay(sp2_ctx *ctx, const sp2_tape *tape, const sp2_bsr *F, sp2_bsr **D_out) {
+  return guarded(ctx, [&]() {
+    if (!tape || !D_out) fail(SP2_ERR_INVALID_ARG, "NULL tape or output");
+    *D_out = nullptr;
+    *D_out = run_replay(*ctx, *tape, F);
+    return SP2_OK;
+  });
+}
+
+int sp2_tape_info(const sp2_tape *tape, int32_t *n_iter, int32_t *n_checkpoints, int64_t *device_bytes) {
+  if (!tape) return SP2_ERR_INVALID_ARG;
+  if (n_iter) *n_iter = tape->n_iter;
+  if (n_checkpoints) *n_checkpoints = tape->n_ckpt;
+  if (device_bytes) *device_bytes = tape->bytes;
+  return SP2_OK;
+}
+
+int sp2_square_step(sp2_ctx *ctx, const sp2_bsr *Xin, double a, double b, double cc, int precision,
+                    sp2_bsr **Xn_out, double sums[4]) {
+  return guarded(ctx, [&]() {
+    if (!Xn_out) fail(SP2_ERR_INVALID_ARG, "NULL output");
+    *Xn_out = nullptr;
+    if (precision < 0 || precision > 2) fail(SP2_ERR_INVALID_ARG, "unknown precision");
+    DMat X = borrow_matrix(*ctx, Xin, "X");
+    check_finite(*ctx, Xin->val, Xin->nnzb * (int64_t)BB, "X");
+    int mode = M_F64;
+    if (precision != SP2_PREC_FP64) {
+      X = compact_values(*ctx, X, P32);
+      mode = precision == SP2_PREC_FP32 ? M_F32 : M_BF16X3;
+    }
+    Maps m = build_maps(*ctx, X.pat, true);
+    SquareOut so = square_step(*ctx, X, m, mode, X.pool->prec, a, b, cc);
+    if (sums) {
+      sums[0] = so.sums[0];
+      sums[1] = so.sums[1];
+      sums[2] = so.sums[2];
+      sums[3] = so.sums[4] * 2.0 * B * B * B;
+    }
+    *Xn_out = export_bsr(*ctx, so.next);
+    return SP2_OK;
+  });
+}
+
+int sp2_truncate(sp2_ctx *ctx, const sp2_bsr *Xin, double tau, int norm, int64_t coarse_bs, sp2_bsr **Xt_out,
+                 double err[2]) {
+  return guarded(ctx, [&]() {
+    if (!Xt_out) fail(SP2_ERR_INVALID_ARG, "NULL output");
+    *Xt_out = nullptr;
+    if (norm < 0 || norm > 2) fail(SP2_ERR_INVALID_ARG, "unknown truncation norm");
+    if (!(tau >= 0.0)) fail(SP2_ERR_INVALID_ARG, "tau must be >= 0");
+    DMat X = borrow_matrix(*ctx, Xin, "X");
+    check_finite(*ctx, Xin->val, Xin->nnzb * (int64_t)BB, "X");
+    // diagonal blocks are never removed: the input must store all of them
+    {
+      Buf cnt = ctx->alloc(sizeof(int64_t) * X.pat.nbr);
+      launch_diag_missing(*ctx, X.pat.row_ptr.as<int64_t>(), X.pat.col_idx.as<int32_t>(), X.pat.nbr,
+                          cnt.as<int64_t>());
+      Buf tot = ctx->alloc(sizeof(int64_t) * (X.pat.nbr + 1));
+      scan_exclusive_i64(*ctx, cnt.as<int64_t>(), tot.as<int64_t>(), X.pat.nbr);
+      int64_t t = 0;
+      ctx->d2h(&t, tot.as<int64_t>() + X.pat.nbr, sizeof(t));
+      if (t != X.pat.nnzb) fail(SP2_ERR_INVALID_ARG, "X must store every diagonal block");
+    }
+    Buf nrm2 = norms_of(*ctx, X);
+    TruncResult tr = truncate_matrix(*ctx, X, nrm2.as<double>(), tau, norm, coarse_bs);
+    if (err) {
+      err[0] = tr.err_frob;
+      err[1] = tr.err_mixed;
+    }
+    *Xt_out = export_bsr(*ctx, X);
+    return SP2_OK;
+  });
+}
+
+int sp2_bsr_copy(sp2_ctx *ctx, const sp2_bsr *src, int64_t *row_ptr, int32_t *col_idx, double *val) {
+  return guarded(ctx, [&]() {
+    if (!src) fail(SP2_ERR_INVALID_ARG, "NULL matrix");
+    if (!row_ptr || (src->nnzb > 0 && (!col_idx || !val))) fail(SP2_ERR_INVALID_ARG, "NULL destination");
+    SP2_HIP(hipMemcpyAsync(row_ptr, src->row_ptr, sizeof(int64_t) * (src->nbr + 1), hipMemcpyDeviceToDevice,
+                           ctx->stream));
+    if (src->nnzb > 0) {
+      SP2_HIP(hipMemcpyAsync(col_idx, src->col_idx, sizeof(int32_t) * src->nnzb, hipMemcpyDeviceToDevice,
+                             ctx->stream));
+      SP2_HIP(hipMemcpyAsync(val, src->val, sizeof(double) * BB * src->nnzb, hipMemcpyDeviceToDevice, ctx->stream));
+    }
+    ctx->sync();
+    return SP2_OK;
+  });
+}
+
+void sp2_bsr_free(sp2_ctx *ctx, sp2_bsr *m) {
+  if (!m || !m->owned) return;
+  if (ctx) (void)hipSetDevice(ctx->device);
+  delete reinterpret_cast<OwnedBsr *>(m);
+}
+
+void sp2_tape_free(sp2_ctx *ctx, sp2_tape *tape) {
+  if (!tape) return;
+  if (ctx) (void)hipSetDevice(ctx->device);
+  delete tape;
+}
+
+}  // extern "C"

@@ -1,0 +1,94 @@
+"""GPU parity of the hand-written adjoint (VJP / JVP / replay with sqrt(n)
+checkpoints) against the oracle's adjoint of the same frozen map, plus
+finite differences, the dot-product test and the Daleckii-Krein closed form."""
+import numpy as np
+import pytest
+
+from fockgen import bsr_to_dense, dense_spectrum, dense_to_bsr, lattice_fock, random_sym_on_pattern
+from oracle import sp2_oracle as O
+
+from gpu_helpers import rel, to_dense, upper_mask
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lattice_run(gpu_lib):
+    sp2 = gpu_lib
+    Fh, info = lattice_fock(6, seed=0)
+    Fd = bsr_to_dense(Fh)
+    no = info["n_occ"]
+    lmin, lmax = O.gershgorin_bounds(Fd)
+    kw = dict(accel=True, trunc_norm="frobinf", tau_fixed=1e-2, coarse_bs=128)
+    ref = O.sp2(Fd, no, lmin, lmax, -0.37, 0.34, keep_tape=True, **kw)
+    F = sp2.BsrMatrix.from_host(Fh)
+    r = sp2.density(F, no, lmin, lmax, -0.37, 0.34, record_tape=True, **kw)
+    assert r.n_iter == ref.n and np.array_equal(upper_mask(r.D), np.triu(ref.mask))
+    assert list(r.iters["nnzb"]) == list(ref.nnzb)
+    Wh = random_sym_on_pattern(Fh, 1.0, seed=2)
+    dFh = random_sym_on_pattern(Fh, 1e-3, seed=1)
+    return sp2, Fh, Fd, F, r, ref, Wh, dFh
+
+
+def test_vjp_matches_oracle(lattice_run):
+    sp2, Fh, Fd, F, r, ref, Wh, dFh = lattice_run
+    g = to_dense(r.tape.vjp(sp2.BsrMatrix.from_host(Wh)))
+    g_ref = O.vjp(ref, Fd, bsr_to_dense(Wh))
+    assert rel(g, g_ref) <= 1e-10
+
+
+def test_jvp_matches_oracle(lattice_run):
+    sp2, Fh, Fd, F, r, ref, Wh, dFh = lattice_run
+    d = to_dense(r.tape.jvp(sp2.BsrMatrix.from_host(dFh)))
+    d_ref = O.jvp(ref, Fd, bsr_to_dense(dFh))
+    assert rel(d, d_ref) <= 1e-10
+
+
+def test_replay_reproduces_forward_bitwise(lattice_run):
+    sp2, Fh, Fd, F, r, ref, Wh, dFh = lattice_run
+    D2 = r.tape.replay(F)
+    assert np.array_equal(to_dense(D2), to_dense(r.D))
+
+
+def test_finite_differences_and_dot_product(lattice_run):
+    sp2, Fh, Fd, F, r, ref, Wh, dFh = lattice_run
+    h = 1e-5
+    Fp = sp2.BsrMatrix.from_host(Fh.with_values(Fh.val + h * dFh.val))
+    Fm = sp2.BsrMatrix.from_host(Fh.with_values(Fh.val - h * dFh.val))
+    fd = (to_dense(r.tape.replay(Fp)) - to_dense(r.tape.replay(Fm))) / (2 * h)
+    jv = to_dense(r.tape.jvp(sp2.BsrMatrix.from_host(dFh)))
+    assert rel(fd, jv) <= 1e-6
+    W = bsr_to_dense(Wh)
+    g = to_dense(r.tape.vjp(sp2.BsrMatrix.from_host(Wh)))
+    lhs = float(np.sum(W * jv))
+    rhs = float(np.sum(g * bsr_to_dense(dFh)))
+    assert lhs == pytest.approx(rhs, rel=1e-10)
+
+
+@pytest.mark.parametrize("nck", [1, 3, 0])
+def test_checkpoint_counts_same_gradient(lattice_run, nck):
+    sp2, Fh, Fd, F, r, ref, Wh, dFh = lattice_run
+    no = ref.n_occ
+    kw = dict(accel=True, trunc_norm="frobinf", tau_fixed=1e-2, coarse_bs=128)
+    r2 = sp2.density(F, no, ref.lmin, ref.lmax, -0.37, 0.34, record_tape=True, n_checkpoints=nck, **kw)
+    info = r2.tape.info()
+    if nck > 0:
+        assert info["n_checkpoints"] <= nck + 1
+    else:
+        assert info["n_checkpoints"] <= int(np.ceil(np.sqrt(r2.n_max + 1))) + 1
+    g0 = to_dense(r.tape.vjp(sp2.BsrMatrix.from_host(Wh)))
+    g1 = to_dense(r2.tape.vjp(sp2.BsrMatrix.from_host(Wh)))
+    assert np.array_equal(g0, g1)
+
+
+def test_vjp_daleckii_krein_dense(gpu_lib):
+    sp2 = gpu_lib
+    Fd, lam, Y = dense_spectrum(256, seed=2)
+    r = sp2.density(sp2.BsrMatrix.from_host(dense_to_bsr(Fd)), 128, -1.0, 1.0, -0.1, 0.1, trunc_norm="none",
+                    idem_stop=1e-12, record_tape=True)
+    rng = np.random.default_rng(11)
+    A = rng.normal(size=(256, 256))
+    W = np.triu(A) + np.triu(A, 1).T
+    g = to_dense(r.tape.vjp(sp2.BsrMatrix.from_host(dense_to_bsr(W))))
+    g_dk = O.daleckii_krein_gradient(Fd, 128, W)
+    assert rel(g, g_dk) <= 1e-8

@@ -1,0 +1,145 @@
+"""End-to-end GPU parity of sp2_density against the oracle through the C ABI:
+same iteration count, polynomial sequence and scale-and-fold parameters,
+e_i and t_i, block masks, D and homo/lumo estimates."""
+import numpy as np
+import pytest
+
+from fockgen import bsr_to_dense, dense_spectrum, dense_to_bsr, lattice_fock
+from oracle import sp2_oracle as O
+
+from gpu_helpers import rel, to_dense, upper_mask
+
+pytestmark = pytest.mark.gpu
+
+
+def _compare_runs(r, ref, d_tol=1e-9):
+    """FP64 parity bar: e_i and t_i agree to 1e-10 relative plus an absolute
+    floor of 1e-12 sqrt(N) (round-off of X - X^2 when X is nearly idempotent);
+    p_i, alpha_i, n and the masks agree exactly."""
+    N = ref.D.shape[0]
+    e_gpu, e_ref = r.iters["e"], np.array(ref.e)
+    de = np.abs(e_gpu[: len(e_ref)] - e_ref) if len(e_gpu) == len(e_ref) else None
+    print(f"n={r.n_iter}/{ref.n} max|de|={None if de is None else de.max():.3e}")
+    assert r.n_iter == ref.n
+    assert list(r.iters["p"][1:]) == list(ref.p[1:])
+    assert np.array_equal(r.iters["alpha"], np.array(ref.alpha))
+    atol = 1e-12 * np.sqrt(N)
+    assert np.allclose(e_gpu, e_ref, rtol=1e-10, atol=atol)
+    assert np.allclose(r.iters["t"], ref.t, rtol=1e-10, atol=atol)
+    assert list(r.iters["nnzb"]) == list(ref.nnzb)
+    assert np.array_equal(upper_mask(r.D), np.triu(ref.mask))
+    assert rel(to_dense(r.D), ref.D) <= d_tol
+    for a, b in ((r.homo_est, ref.homo_ub_est), (r.lumo_est, ref.lumo_lb_est)):
+        if np.isnan(b):
+            assert np.isnan(a)
+        else:
+            assert a == pytest.approx(b, abs=1e-9)
+
+
+@pytest.mark.parametrize("accel", [False, True])
+def test_dense_c0(gpu_lib, accel):
+    sp2 = gpu_lib
+    Fd, lam, Y = dense_spectrum(512, seed=0)
+    ref = O.sp2(Fd, 256, -1.0, 1.0, -0.1, 0.1, accel=accel, trunc_norm=O.TRUNC_NONE, idem_stop=1e-12)
+    F = sp2.BsrMatrix.from_host(dense_to_bsr(Fd))
+    r = sp2.density(F, 256, -1.0, 1.0, -0.1, 0.1, accel=accel, trunc_norm="none", idem_stop=1e-12)
+    _compare_runs(r, ref)
+    D_eig = Y[:, :256] @ Y[:, :256].T
+    assert np.linalg.norm(to_dense(r.D) - D_eig) <= 1e-10
+    assert r.stop_reason == ref.stop_reason
+
+
+@pytest.mark.parametrize("L,norm,tau,cbs", [
+    (6, "frobinf", 1e-3, 256),
+    (6, "frob", 3e-3, 4096),
+    (8, "frobinf", 1e-3, 512),
+    (8, "frobinf", 1e-2, 256),
+])
+def test_lattice_truncated(gpu_lib, L, norm, tau, cbs):
+    sp2 = gpu_lib
+    Fh, info = lattice_fock(L, seed=0)
+    Fd = bsr_to_dense(Fh)
+    no = info["n_occ"]
+    lmin, lmax = O.gershgorin_bounds(Fd)
+    lam = np.linalg.eigvalsh(Fd)
+    h, lu = lam[no - 1] + 0.01, lam[no] - 0.01
+    ref = O.sp2(Fd, no, lmin, lmax, h, lu, accel=True, trunc_norm=norm, tau_fixed=tau, coarse_bs=cbs)
+    r = sp2.density(sp2.BsrMatrix.from_host(Fh), no, lmin, lmax, h, lu, accel=True, trunc_norm=norm,
+                    tau_fixed=tau, coarse_bs=cbs)
+    assert sum(t.removed for t in ref.trunc) > 0
+    _compare_runs(r, ref)
+    assert np.allclose(r.iters["trunc_err_mixed"], [t.err_mixed for t in ref.trunc], rtol=1e-9, atol=1e-300)
+
+
+def test_gamma_schedule_and_bound(gpu_lib):
+    sp2 = gpu_lib
+    Fh, info = lattice_fock(8, seed=0)
+    Fd = bsr_to_dense(Fh)
+    no = info["n_occ"]
+    lmin, lmax = O.gershgorin_bounds(Fd)
+    ref = O.sp2(Fd, no, lmin, lmax, -0.31, 0.33, accel=True, trunc_norm="frobinf", gamma=0.05, coarse_bs=256)
+    r = sp2.density(sp2.BsrMatrix.from_host(Fh), no, lmin, lmax, -0.31, 0.33, accel=True, trunc_norm="frobinf",
+                    gamma=0.05, coarse_bs=256)
+    _compare_runs(r, ref)
+    assert np.allclose(r.iters["tau"], ref.tau, rtol=1e-15, atol=0)
+    assert r.subspace_err_bound == pytest.approx(ref.subspace_err_bound, rel=1e-9)
+
+
+def test_trace_correcting_two_run_protocol(gpu_lib):
+    sp2 = gpu_lib
+    Fh, info = lattice_fock(6, seed=0)
+    Fd = bsr_to_dense(Fh)
+    no = info["n_occ"]
+    lmin, lmax = O.gershgorin_bounds(Fd)
+    ref1 = O.sp2(Fd, no, lmin, lmax, trunc_norm="frobinf", tau_fixed=1e-3, coarse_bs=256)
+    F = sp2.BsrMatrix.from_host(Fh)
+    r1 = sp2.density(F, no, lmin, lmax, trunc_norm="frobinf", tau_fixed=1e-3, coarse_bs=256)
+    _compare_runs(r1, ref1)
+    ref2 = O.sp2(Fd, no, lmin, lmax, ref1.homo_ub_est, ref1.lumo_lb_est, trunc_norm="frobinf", tau_fixed=1e-3,
+                 coarse_bs=256)
+    r2 = sp2.density(F, no, lmin, lmax, ref1.homo_ub_est, ref1.lumo_lb_est, trunc_norm="frobinf", tau_fixed=1e-3,
+                     coarse_bs=256)
+    _compare_runs(r2, ref2)
+
+
+def test_error_codes(gpu_lib):
+    sp2 = gpu_lib
+    Fd, lam, Y = dense_spectrum(128, seed=3)
+    F = sp2.BsrMatrix.from_host(dense_to_bsr(Fd))
+    with pytest.raises(sp2.Sp2Error) as e:
+        sp2.density(F, 64, -1.0, 1.0, 0.2, 0.1)
+    assert e.value.code == -2
+    with pytest.raises(sp2.Sp2Error) as e:
+        sp2.density(F, 0, -1.0, 1.0)
+    assert e.value.code == -1
+    with pytest.raises(sp2.Sp2Error) as e:
+        sp2.density(F, 64, 1.0, -1.0)
+    assert e.value.code == -1
+    bad = dense_to_bsr(Fd)
+    bad.val[0, 3, 5] = np.nan
+    with pytest.raises(sp2.Sp2Error) as e:
+        sp2.density(sp2.BsrMatrix.from_host(bad), 64, -1.0, 1.0)
+    assert e.value.code == -3
+    # wrong bounds: the true homo lies above the given homo_ub -> trace warning or non-convergence
+    r = sp2.density(F, 64, -1.0, 1.0, lam[63] - 0.3, lam[63] - 0.25, trunc_norm="none")
+    assert r.status in (1, 2)
+
+
+def test_mixed_fp32_reports_error(gpu_lib):
+    sp2 = gpu_lib
+    Fh, info = lattice_fock(8, seed=0)
+    Fd = bsr_to_dense(Fh)
+    no = info["n_occ"]
+    lmin, lmax = O.gershgorin_bounds(Fd)
+    F = sp2.BsrMatrix.from_host(Fh)
+    r64 = sp2.density(F, no, lmin, lmax, -0.31, 0.33, trunc_norm="frobinf", tau_fixed=1e-6, coarse_bs=512)
+    r32 = sp2.density(F, no, lmin, lmax, -0.31, 0.33, trunc_norm="frobinf", tau_fixed=1e-6, coarse_bs=512,
+                      precision="fp32")
+    assert r32.switch_iter >= 1
+    assert set(r32.iters["precision"][: r32.switch_iter]) == {1}
+    assert set(r32.iters["precision"][r32.switch_iter:]) == {0}
+    D64, D32 = to_dense(r64.D), to_dense(r32.D)
+    err = np.linalg.norm(D32 - D64)
+    print(f"mixed fp32 vs fp64: ||dD||_F = {err:.3e}, n = {r32.n_iter} vs {r64.n_iter}")
+    assert err <= 1e-3
+    assert abs(np.trace(D32) - no) <= 1e-6

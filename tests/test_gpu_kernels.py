@@ -1,0 +1,139 @@
+"""GPU parity of the single steps of the hot path against the oracle, through
+the C ABI: symbolic + numeric square with the fused update and reductions,
+truncation, Gershgorin bounds."""
+import math
+
+import numpy as np
+import pytest
+
+from fockgen import BSR, bsr_to_dense, lattice_fock, random_sym_bsr
+from oracle import sp2_oracle as O
+
+from gpu_helpers import rel, to_dense, upper_mask
+
+pytestmark = pytest.mark.gpu
+
+CASES = [  # (n, density, seed)
+    (64, 1.0, 0),
+    (200, 1.0, 1),      # ragged: 4 block rows, last one 8 rows
+    (1000, 0.35, 2),    # 16 block rows, ragged, sparse pattern
+    (1500, 0.12, 3),    # very sparse
+]
+
+
+def _oracle_square(X, n, a, b, c):
+    """a I + b X + c X^2 restricted to the block pattern of X^2 (plain dense)."""
+    Xd = bsr_to_dense(X)
+    S = Xd @ Xd
+    M = O.structural_mask(Xd, 64) | np.eye(X.nbr, dtype=bool)
+    # the stored pattern, including exactly-zero stored blocks
+    Mst = np.zeros((X.nbr, X.nbr), dtype=bool)
+    Mst[X.rows(), X.col_idx] = True
+    Mst = Mst | Mst.T
+    MS = O.pattern_square(Mst)
+    out = a * np.eye(n) + b * Xd + c * S
+    out = out * O.expand_mask(MS, n, 64)
+    return Xd, S, out, MS, Mst
+
+
+@pytest.mark.parametrize("n,dens,seed", CASES)
+def test_square_step_fp64(gpu_lib, n, dens, seed):
+    sp2 = gpu_lib
+    Xh = random_sym_bsr(n, dens, seed=seed, std=0.1)
+    a, b, c = 0.3, -0.7, 1.3
+    X = sp2.BsrMatrix.from_host(Xh)
+    Y, sums = sp2.square_step(X, a, b, c, "fp64")
+    Xd, S, ref, MS, Mst = _oracle_square(Xh, n, a, b, c)
+    # output pattern is exactly the block pattern of X^2 (upper)
+    assert np.array_equal(upper_mask(Y), np.triu(MS))
+    Yd = to_dense(Y)
+    assert rel(Yd, ref) <= 1e-13
+    e2 = float(np.sum((Xd - S) ** 2))
+    assert sums[0] == pytest.approx(e2, rel=1e-12)
+    assert sums[1] == pytest.approx(np.trace(Xd), rel=1e-12, abs=1e-12)
+    assert sums[2] == pytest.approx(np.trace(S), rel=1e-12)
+    assert sums[3] == 2.0 * 64 ** 3 * O._triples_upper(Mst)
+
+
+@pytest.mark.parametrize("n,dens,seed", CASES[1:3])
+def test_square_step_fp32(gpu_lib, n, dens, seed):
+    sp2 = gpu_lib
+    Xh = random_sym_bsr(n, dens, seed=seed, std=0.1)
+    X = sp2.BsrMatrix.from_host(Xh)
+    Y, sums = sp2.square_step(X, 0.0, 2.0, -1.0, "fp32")
+    Xd, S, ref, MS, Mst = _oracle_square(Xh, n, 0.0, 2.0, -1.0)
+    assert np.array_equal(upper_mask(Y), np.triu(MS))
+    # FP32 inputs and products (unit roundoff 2^-24), accumulated over <= n terms
+    Xa = np.abs(Xd)
+    bound = 4 * 2.0 ** -24 * (2 * Xa + (n + 2) * (Xa @ Xa)) + 1e-30
+    assert np.all(np.abs(to_dense(Y) - ref) <= bound)
+
+
+def _spread_bsr(n, seed, dens=0.8):
+    """Random symmetric BSR whose block norms span many decades."""
+    M = random_sym_bsr(n, dens, seed=seed)
+    rng = np.random.default_rng(seed + 50)
+    scale = 10.0 ** rng.uniform(-7, 0, size=M.nnzb)
+    I = M.rows()
+    scale[I == M.col_idx] = 1.0
+    return M.with_values(M.val * scale[:, None, None])
+
+
+@pytest.mark.parametrize("norm,cbs", [("frob", 4096), ("frobinf", 256), ("frobinf", 128), ("frobinf", 4096)])
+@pytest.mark.parametrize("tau", [1e-6, 1e-4, 1e-2])
+def test_truncate_matches_oracle(gpu_lib, norm, cbs, tau):
+    sp2 = gpu_lib
+    Mh = _spread_bsr(1100, seed=7)
+    Md = bsr_to_dense(Mh)
+    mask = np.zeros((Mh.nbr, Mh.nbr), dtype=bool)
+    mask[Mh.rows(), Mh.col_idx] = True
+    mask = mask | mask.T
+    Xt_ref, Mt_ref, info = O.truncate(Md, mask, tau, norm, 64, cbs)
+    Xt, err = sp2.truncate(sp2.BsrMatrix.from_host(Mh), tau, norm, cbs)
+    got = upper_mask(Xt)
+    assert np.array_equal(got, np.triu(Mt_ref)), "removed block sets differ"
+    assert info.removed > 0 or tau == 1e-6
+    assert err[0] == pytest.approx(info.err_frob, rel=1e-12, abs=1e-300)
+    assert err[1] == pytest.approx(info.err_mixed, rel=1e-12, abs=1e-300)
+    assert np.array_equal(to_dense(Xt), Xt_ref)
+
+
+def test_truncate_ties_in_block_order(gpu_lib):
+    """Equal block norms are removed in (I, J) order."""
+    sp2 = gpu_lib
+    n, nbr = 256, 4
+    vals, rows, cols = [], [], []
+    for I in range(nbr):
+        for J in range(I, nbr):
+            blk = np.full((64, 64), 1e-3) if I != J else np.eye(64)
+            rows.append(I)
+            cols.append(J)
+            vals.append(blk)
+    rp = np.zeros(nbr + 1, dtype=np.int64)
+    np.add.at(rp, np.array(rows) + 1, 1)
+    Mh = BSR(n, np.cumsum(rp), np.array(cols, dtype=np.int32), np.array(vals))
+    # each off-diagonal block: weight 2 * 4096 * 1e-6; budget fits exactly 2 of 6
+    tau = math.sqrt(2 * 2 * 4096 * 1e-6) * (1 + 1e-12)
+    Xt, err = sp2.truncate(sp2.BsrMatrix.from_host(Mh), tau, "frob")
+    m = upper_mask(Xt)
+    removed = [(I, J) for I in range(nbr) for J in range(I + 1, nbr) if not m[I, J]]
+    assert removed == [(0, 1), (0, 2)]
+
+
+@pytest.mark.parametrize("L", [4, 6, 8])
+def test_gershgorin(gpu_lib, L):
+    sp2 = gpu_lib
+    Fh, _ = lattice_fock(L, seed=L)
+    lo, hi = sp2.gershgorin(sp2.BsrMatrix.from_host(Fh))
+    rlo, rhi = O.gershgorin_bounds(bsr_to_dense(Fh))
+    assert lo == pytest.approx(rlo, rel=1e-13)
+    assert hi == pytest.approx(rhi, rel=1e-13)
+
+
+def test_deterministic_square(gpu_lib):
+    sp2 = gpu_lib
+    X = sp2.BsrMatrix.from_host(random_sym_bsr(1000, 0.5, seed=11))
+    Y1, s1 = sp2.square_step(X, 0.1, 0.2, 0.3)
+    Y2, s2 = sp2.square_step(X, 0.1, 0.2, 0.3)
+    assert s1 == s2
+    assert bool((Y1.val == Y2.val).all())
