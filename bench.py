@@ -40,9 +40,9 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(L=10, tau=1e-6):
+def cpu_baseline(L=12, tau=1e-6):
     """The CPU oracle (dense FP64 NumPy, unchanged) on a bounded sample: one
-    SP2ACC run on the 10 x 10 x 10 lattice (N = 4000) of the same generator
+    SP2ACC run on the 12 x 12 x 12 lattice (N = 6912) of the same generator
     and options, with homo/lumo bounds from diagonalisation widened by 1% of
     the gap."""
     import numpy as np
@@ -80,6 +80,10 @@ def main():
     ap.add_argument("--config", default="c1", choices=sorted(CONFIGS))
     ap.add_argument("--precision", default=None, choices=["fp64", "fp32", "bf16x3"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="copy a buffer of this size once before timing (reference for HBM traffic counters)")
+    ap.add_argument("--bounds", default=None,
+                    help="homo_ub,lumo_lb known in advance (e.g. from a previous SCF cycle): skips the first run")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (the method runs on one GPU with no sharding); got --gpus {args.gpus}",
@@ -104,11 +108,23 @@ def main():
     no = info["n_occ"]
     lmin, lmax = sp2.gershgorin(F)
     opts = dict(accel=True, trunc_norm="frobinf", tau_fixed=tau, coarse_bs=4096)
-    t = time.perf_counter()
-    r1 = sp2.density(F, no, lmin, lmax, **opts)
-    log(f"run 1 (trace-correcting): n={r1.n_iter} homo<={r1.homo_est:.6f} lumo>={r1.lumo_est:.6f} "
-        f"{time.perf_counter() - t:.2f} s")
-    hub, llb = r1.homo_est, r1.lumo_est
+    if args.bounds:
+        hub, llb = (float(x) for x in args.bounds.split(","))
+    else:
+        t = time.perf_counter()
+        r1 = sp2.density(F, no, lmin, lmax, **opts)
+        log(f"run 1 (trace-correcting): n={r1.n_iter} homo<={r1.homo_est!r} lumo>={r1.lumo_est!r} "
+            f"{time.perf_counter() - t:.2f} s")
+        hub, llb = r1.homo_est, r1.lumo_est
+
+    if args.calibrate_copy_mib > 0:
+        nb = args.calibrate_copy_mib << 20
+        src = torch.ones(nb, dtype=torch.uint8, device="cuda:0")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"calibration copy: {nb} bytes read, {nb} bytes written")
+        del src, dst
 
     def step():
         return sp2.density(F, no, lmin, lmax, hub, llb, precision=prec, **opts)
@@ -130,6 +146,13 @@ def main():
         ksq.append(res.square_time_s)
         log(f"step {k}: n={res.n_iter} {dt:.3f} s  {res.alg_flops / dt / 1e12:.2f} TFLOP/s  "
             f"square kernels {res.square_time_s:.3f} s")
+        if k == 0:
+            it = res.iters
+            for i in range(res.n_iter + 1):
+                ks = it["square_time_s"][i]
+                log(f"   iter {i:2d} p={it['p'][i]:2d} nnzb={it['nnzb'][i]:7d} e={it['e'][i]:.3e} "
+                    f"flops={it['iter_flops'][i] / 1e12:8.3f} TF  square {ks * 1e3:8.2f} ms  "
+                    f"{it['iter_flops'][i] / max(ks, 1e-12) / 1e12:6.2f} TF/s  wall {it['iter_time_s'][i] * 1e3:8.2f} ms")
     total = time.perf_counter() - t_all
     ms = 1e3 * total / args.steps
     value = sum(flops) / sum(times) / 1e12

@@ -163,23 +163,26 @@ void launch_update(Ctx &c, const void *xpool, int xprec, const int32_t *xidxmap,
                    const int32_t *out_col, int64_t nout, void *spool, int sprec, double ca, double cb, double cc,
                    int64_t n, double *parts);
 
-// squares (kernels_square.hip)
-struct SquareArgs {
+constexpr int NPART = 5;  // per output block: e2 (weighted), trX, trS, ||out||^2, #K
+
+// tiled square: one workgroup per 2 x 2 tile of output blocks (kernels_tile.hip)
+struct TileArgs {
   const void *xpool;
   int xprec;
-  const int32_t *idxmap;
-  const uint32_t *bits;
+  const int32_t *idxmap;   // slot map of X
+  const uint32_t *bits;    // block-row bitmaps of X
   int nbr, W;
-  const int32_t *out_row, *out_col;
-  int64_t nout;
-  void *opool;
+  const int32_t *oidx;     // nbr x nbr: pattern position of output block (I, J), or -1
+  const int32_t *tiles;    // ntiles pairs (TI, TJ), TI <= TJ in units of 2 blocks
+  int64_t ntiles;
+  void *opool;             // output block at its pattern position
   int oprec;
   double ca, cb, cc;
   int64_t n;
-  double *parts;  // nout x NPART
+  double *parts;           // by pattern position, NPART each
 };
-constexpr int NPART = 5;  // e2 (weighted), trX, trS, ||out||^2, #K
-void launch_square(Ctx &c, int mode, const SquareArgs &a);
+int64_t build_tiles(Ctx &c, const int32_t *oidx, int nbr, Buf &tiles);
+void launch_square_tile(Ctx &c, int mode, const TileArgs &a);
 
 // anticommutator products for the adjoint (kernels_square.hip)
 struct AntiArgs {

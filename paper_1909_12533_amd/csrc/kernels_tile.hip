@@ -1,0 +1,298 @@
+// Tiled numeric block-sparse symmetric square (the hot kernel of Algorithm 2)
+// with the polynomial update, idempotency error and traces in its epilogue.
+//
+// Work decomposition: one workgroup per 2 x 2 tile of output blocks
+// (I0, I0+1) x (J0, J0+1), I0 <= J0 in tile units; wave w computes the whole
+// 64 x 64 output block (I0 + w / 2, J0 + w % 2) as 4 x 4 MFMA 16 x 16 tiles.
+// The K loop runs over the set bits of (bits[I0] | bits[I0+1]) &
+// (bits[J0] | bits[J0+1]), which is exactly the union of the four blocks'
+// K sets.  Per K the four operand blocks X_{I0,K}, X_{I0+1,K}, X_{K,J0},
+// X_{K,J0+1} are staged through LDS once and each is used by two waves, so
+// every 32 KB loaded from global memory feeds 2 x 64^3 x 2 flops; a wave
+// whose own pair of blocks is absent for this K skips its MFMAs.  Lower
+// blocks X_KI (K > I) are read as transposes of the stored X_IK by the
+// fragment addressing.  The next K's four blocks are loaded into registers
+// while the current K's MFMAs run.
+#include "mfma.h"
+
+namespace sp2 {
+
+namespace {
+
+using namespace dev;
+
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+// 16-deep k chunk fragments for a wave computing a full 64 x 64 block:
+// four 16-row A tiles and four 16-column B tiles, k index k0 + 4 g + s for
+// MFMA s of the chunk (lane group g = lane / 16).
+template <typename T, bool TA, bool TB> struct Frag4 {
+  T a[4][4], b[4][4];
+  __device__ inline void load(const T *As, const T *Bs, int k0) {
+    constexpr int LD = MF<T>::LD;
+    const int lane = threadIdx.x & 63;
+    const int l16 = lane & 15, kb = k0 + 4 * (lane >> 4);
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const int r = 16 * m + l16;
+      if (!TA) {
+        const T *p = As + r * LD + kb;
+#pragma unroll
+        for (int s = 0; s < 4; ++s) a[m][s] = p[s];
+      } else {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) a[m][s] = As[(kb + s) * LD + r];
+      }
+    }
+#pragma unroll
+    for (int n = 0; n < 4; ++n) {
+      const int c = 16 * n + l16;
+      if (TB) {
+        const T *p = Bs + c * LD + kb;
+#pragma unroll
+        for (int s = 0; s < 4; ++s) b[n][s] = p[s];
+      } else {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) b[n][s] = Bs[(kb + s) * LD + c];
+      }
+    }
+  }
+};
+
+template <typename T, bool TA, bool TB>
+__device__ inline void mma_full(typename MF<T>::acc_t (&acc)[4][4], const T *As, const T *Bs) {
+  Frag4<T, TA, TB> f;
+#pragma unroll
+  for (int kc = 0; kc < 4; ++kc) {
+    f.load(As, Bs, 16 * kc);
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int n = 0; n < 4; ++n) acc[m][n] = MF<T>::op(f.a[m][s], f.b[n][s], acc[m][n]);
+  }
+}
+
+template <typename T>
+__device__ inline void mma_dispatch(typename MF<T>::acc_t (&acc)[4][4], const T *As, const T *Bs, bool tA, bool tB) {
+  if (!tA && !tB)
+    mma_full<T, false, false>(acc, As, Bs);
+  else if (!tA && tB)
+    mma_full<T, false, true>(acc, As, Bs);
+  else if (tA && !tB)
+    mma_full<T, true, false>(acc, As, Bs);
+  else
+    mma_full<T, true, true>(acc, As, Bs);
+}
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+template <typename T, typename TO>
+__global__ __launch_bounds__(TPB, 1) void k_square_tile(TileArgs a) {
+  constexpr int LD = MF<T>::LD;
+  __shared__ __align__(16) T As[2][64 * LD];
+  __shared__ __align__(16) T Bs[2][64 * LD];
+  const int64_t t = blockIdx.x;
+  if (t >= a.ntiles) return;
+  const int nbr = a.nbr, W = a.W;
+  const int I0 = 2 * __builtin_amdgcn_readfirstlane(a.tiles[2 * t]);
+  const int J0 = 2 * __builtin_amdgcn_readfirstlane(a.tiles[2 * t + 1]);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int ia = wave >> 1, jb = wave & 1;
+  const int I = I0 + ia, J = J0 + jb;
+  const bool has_i1 = I0 + 1 < nbr, has_j1 = J0 + 1 < nbr;
+  int32_t pos = -1;
+  if (I < nbr && J < nbr && I <= J) pos = __builtin_amdgcn_readfirstlane(a.oidx[(int64_t)I * nbr + J]);
+  const T *xp = static_cast<const T *>(a.xpool);
+
+  typename MF<T>::acc_t acc[4][4];
+#pragma unroll
+  for (int m = 0; m < 4; ++m)
+#pragma unroll
+    for (int n = 0; n < 4; ++n) acc[m][n] = typename MF<T>::acc_t{0, 0, 0, 0};
+
+  // K over the union of the four blocks' K sets
+  const uint32_t *bI0 = a.bits + (int64_t)I0 * W, *bI1 = a.bits + (int64_t)(has_i1 ? I0 + 1 : I0) * W;
+  const uint32_t *bJ0 = a.bits + (int64_t)J0 * W, *bJ1 = a.bits + (int64_t)(has_j1 ? J0 + 1 : J0) * W;
+  int wi = -1;
+  uint32_t mask = 0u;
+  auto next_k = [&]() -> int {
+    while (mask == 0u) {
+      ++wi;
+      if (wi >= W) return -1;
+      const uint32_t ra = bI0[wi] | (has_i1 ? bI1[wi] : 0u);
+      const uint32_t rb = bJ0[wi] | (has_j1 ? bJ1[wi] : 0u);
+      mask = (uint32_t)__builtin_amdgcn_readfirstlane((int)(ra & rb));
+    }
+    const int K = wi * 32 + __builtin_ctz(mask);
+    mask &= mask - 1u;
+    return K;
+  };
+
+  // staged operand blocks A0 = X_{I0,K}, A1 = X_{I0+1,K}, B0 = X_{K,J0}, B1 = X_{K,J0+1}
+  constexpr int NCH = Stage<T>::NCH;
+  constexpr int QB = BB * (int)sizeof(T) / 16;  // 16-byte chunks per block
+  const u32x4 *xq = reinterpret_cast<const u32x4 *>(xp);
+  u32x4 r0[NCH], r1[NCH], r2[NCH], r3[NCH];
+  int32_t s0 = -1, s1 = -1, s2 = -1, s3 = -1;
+// absent block (slot < 0): zeros, and no load is issued (wave-uniform branch)
+#define SP2_LOAD_BLOCK(R, SL)                                                     \
+  do {                                                                            \
+    if ((SL) >= 0) {                                                              \
+      const u32x4 *src_ = xq + (int64_t)(SL) * QB + threadIdx.x;                  \
+      _Pragma("unroll") for (int j = 0; j < NCH; ++j) R[j] = src_[j * TPB];       \
+    } else {                                                                      \
+      _Pragma("unroll") for (int j = 0; j < NCH; ++j) R[j] = u32x4{0u, 0u, 0u, 0u}; \
+    }                                                                             \
+  } while (0)
+#define SP2_ISSUE(KK)                                                                                 \
+  do {                                                                                                \
+    s0 = __builtin_amdgcn_readfirstlane(a.idxmap[(int64_t)I0 * nbr + (KK)]);                          \
+    s1 = has_i1 ? __builtin_amdgcn_readfirstlane(a.idxmap[(int64_t)(I0 + 1) * nbr + (KK)]) : -1;      \
+    s2 = __builtin_amdgcn_readfirstlane(a.idxmap[(int64_t)(KK) * nbr + J0]);                          \
+    s3 = has_j1 ? __builtin_amdgcn_readfirstlane(a.idxmap[(int64_t)(KK) * nbr + J0 + 1]) : -1;        \
+    SP2_LOAD_BLOCK(r0, s0);                                                                           \
+    SP2_LOAD_BLOCK(r1, s1);                                                                           \
+    SP2_LOAD_BLOCK(r2, s2);                                                                           \
+    SP2_LOAD_BLOCK(r3, s3);                                                                           \
+  } while (0)
+
+  int nk = 0;
+  int K = next_k();
+  if (K >= 0) SP2_ISSUE(K);
+  while (K >= 0) {
+    const int32_t c0 = s0, c1 = s1, c2 = s2, c3 = s3;
+    __syncthreads();  // previous tiles fully consumed
+#pragma unroll
+    for (int j = 0; j < NCH; ++j) {
+      const int e = (j * TPB + (int)threadIdx.x) * Stage<T>::EPC;
+      const int o = (e >> 6) * LD + (e & 63);
+      *reinterpret_cast<u32x4 *>(&As[0][o]) = r0[j];
+      *reinterpret_cast<u32x4 *>(&As[1][o]) = r1[j];
+      *reinterpret_cast<u32x4 *>(&Bs[0][o]) = r2[j];
+      *reinterpret_cast<u32x4 *>(&Bs[1][o]) = r3[j];
+    }
+    __syncthreads();
+    const int Kn = next_k();
+    if (Kn >= 0) SP2_ISSUE(Kn);  // next K's blocks in flight during the MFMAs
+    const int32_t sa = ia ? c1 : c0, sb = jb ? c3 : c2;
+    if (pos >= 0 && sa >= 0 && sb >= 0) {
+      mma_dispatch<T>(acc, ia ? As[1] : As[0], jb ? Bs[1] : Bs[0], I > K, K > J);
+      ++nk;
+    }
+    K = Kn;
+  }
+#undef SP2_ISSUE
+#undef SP2_LOAD_BLOCK
+  if (pos < 0) return;
+
+  // epilogue: X_next = ca I + cb X + cc S on block (I, J); per-block partials
+  const int l16 = lane & 15, g = lane >> 4;
+  const int32_t sx = a.idxmap[(int64_t)I * nbr + J];
+  const T *xb = sx >= 0 ? xp + (int64_t)sx * BB : nullptr;
+  TO *ob = static_cast<TO *>(a.opool) + (int64_t)pos * BB;
+  double e2 = 0.0, tx = 0.0, ts = 0.0, nr = 0.0;
+#pragma unroll
+  for (int m = 0; m < 4; ++m)
+#pragma unroll
+    for (int n = 0; n < 4; ++n)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int r = 16 * m + MF<T>::row(g, q);
+        const int c = 16 * n + l16;
+        const double s = (double)acc[m][n][q];
+        const double x = xb ? (double)xb[r * 64 + c] : 0.0;
+        const bool dg = (I == J) && (r == c);
+        const bool real_dg = dg && ((int64_t)I * B + r < a.n);
+        const double o = a.cc * s + a.cb * x + (real_dg ? a.ca : 0.0);
+        const TO ov = (TO)o;
+        ob[r * 64 + c] = ov;
+        const double od = (double)ov;
+        nr += od * od;
+        const double df = x - s;
+        e2 += df * df;
+        if (dg) {
+          tx += x;
+          ts += s;
+        }
+      }
+  e2 = wave_sum(e2);
+  tx = wave_sum(tx);
+  ts = wave_sum(ts);
+  nr = wave_sum(nr);
+  if (lane == 0) {
+    double *p = a.parts + (int64_t)pos * NPART;
+    p[0] = (I == J) ? e2 : 2.0 * e2;
+    p[1] = tx;
+    p[2] = ts;
+    p[3] = nr;
+    p[4] = (double)nk;
+  }
+}
+
+// flags of 2 x 2 output tiles holding at least one output block
+__global__ void k_tile_flags(const int32_t *oidx, int nbr, int ntr, int64_t *flag) {
+  const int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (id >= (int64_t)ntr * ntr) return;
+  const int TI = (int)(id / ntr), TJ = (int)(id % ntr);
+  int64_t f = 0;
+  if (TI <= TJ) {
+    for (int a = 0; a < 2; ++a)
+      for (int b = 0; b < 2; ++b) {
+        const int I = 2 * TI + a, J = 2 * TJ + b;
+        if (I < nbr && J < nbr && I <= J && oidx[(int64_t)I * nbr + J] >= 0) f = 1;
+      }
+  }
+  flag[id] = f;
+}
+
+__global__ void k_tile_write(const int64_t *flag, const int64_t *pos, int ntr, int32_t *tiles) {
+  const int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (id >= (int64_t)ntr * ntr || !flag[id]) return;
+  const int64_t o = pos[id];
+  tiles[2 * o] = (int32_t)(id / ntr);
+  tiles[2 * o + 1] = (int32_t)(id % ntr);
+}
+
+}  // namespace
+
+int64_t build_tiles(Ctx &c, const int32_t *oidx, int nbr, Buf &tiles) {
+  const int ntr = (nbr + 1) / 2;
+  const int64_t n = (int64_t)ntr * ntr;
+  Buf flag = c.alloc(sizeof(int64_t) * n), pos = c.alloc(sizeof(int64_t) * (n + 1));
+  k_tile_flags<<<(unsigned)((n + TPB - 1) / TPB), TPB, 0, c.stream>>>(oidx, nbr, ntr, flag.as<int64_t>());
+  SP2_LAUNCH_CHECK();
+  scan_exclusive_i64(c, flag.as<int64_t>(), pos.as<int64_t>(), n);
+  int64_t nt = 0;
+  c.d2h(&nt, pos.as<int64_t>() + n, sizeof(int64_t));
+  tiles = c.alloc(sizeof(int32_t) * 2 * (nt > 0 ? nt : 1));
+  k_tile_write<<<(unsigned)((n + TPB - 1) / TPB), TPB, 0, c.stream>>>(flag.as<int64_t>(), pos.as<int64_t>(), ntr,
+                                                                      tiles.as<int32_t>());
+  SP2_LAUNCH_CHECK();
+  return nt;
+}
+
+void launch_square_tile(Ctx &c, int mode, const TileArgs &a) {
+  if (a.ntiles <= 0) return;
+  const unsigned g = (unsigned)a.ntiles;
+  if (mode == M_F64) {
+    if (a.xprec != P64 || a.oprec != P64) fail(SP2_ERR_INVALID_ARG, "FP64 square needs FP64 pools");
+    k_square_tile<double, double><<<g, TPB, 0, c.stream>>>(a);
+  } else if (mode == M_F32) {
+    if (a.xprec != P32) fail(SP2_ERR_INVALID_ARG, "FP32 square needs an FP32 input pool");
+    if (a.oprec == P32)
+      k_square_tile<float, float><<<g, TPB, 0, c.stream>>>(a);
+    else
+      k_square_tile<float, double><<<g, TPB, 0, c.stream>>>(a);
+  } else {
+    fail(SP2_ERR_INVALID_ARG, "square mode not available");
+  }
+  SP2_LAUNCH_CHECK();
+}
+
+}  // namespace sp2

@@ -234,29 +234,33 @@ SquareOut square_step(Ctx &c, const DMat &X, const Maps &m, int mode, int oprec,
   const int64_t nout = r.next.pat.nnzb;
   r.next.pool = new_pool(c, oprec, nout);
   r.parts = c.alloc(sizeof(double) * NPART * (size_t)(nout > 0 ? nout : 1));
-  SquareArgs a;
-  a.xpool = X.pool->vals.p;
-  a.xprec = X.pool->prec;
-  a.idxmap = m.idxmap.as<int32_t>();
-  a.bits = m.bits.as<uint32_t>();
-  a.nbr = X.pat.nbr;
-  a.W = m.W;
-  a.out_row = r.next.pat.row_of.as<int32_t>();
-  a.out_col = r.next.pat.col_idx.as<int32_t>();
-  a.nout = nout;
-  a.opool = r.next.pool->vals.p;
-  a.oprec = oprec;
-  a.ca = ca;
-  a.cb = cb;
-  a.cc = cc;
-  a.n = X.pat.n;
-  a.parts = r.parts.as<double>();
+  // 2 x 2 output tiles over the square's pattern
+  Maps om = build_maps(c, r.next.pat, false);
+  Buf tiles;
+  const int64_t ntiles = build_tiles(c, om.idxmap.as<int32_t>(), X.pat.nbr, tiles);
+  TileArgs ta;
+  ta.xpool = X.pool->vals.p;
+  ta.xprec = X.pool->prec;
+  ta.idxmap = m.idxmap.as<int32_t>();
+  ta.bits = m.bits.as<uint32_t>();
+  ta.nbr = X.pat.nbr;
+  ta.W = m.W;
+  ta.oidx = om.idxmap.as<int32_t>();
+  ta.tiles = tiles.as<int32_t>();
+  ta.ntiles = ntiles;
+  ta.opool = r.next.pool->vals.p;
+  ta.oprec = oprec;
+  ta.ca = ca;
+  ta.cb = cb;
+  ta.cc = cc;
+  ta.n = X.pat.n;
+  ta.parts = r.parts.as<double>();
   EventPair ev;
   SP2_HIP(hipEventRecord(ev.a, c.stream));
-  launch_square(c, mode, a);
+  launch_square_tile(c, mode, ta);
   SP2_HIP(hipEventRecord(ev.b, c.stream));
   Buf sums = c.alloc(sizeof(double) * NPART);
-  launch_reduce_parts(c, r.parts.as<double>(), nout, NPART, sums.as<double>());
+  launch_reduce_parts(c, ta.parts, nout, NPART, sums.as<double>());
   c.d2h(r.sums, sums.p, sizeof(double) * NPART);
   float ms = 0.0f;
   SP2_HIP(hipEventElapsedTime(&ms, ev.a, ev.b));
