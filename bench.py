@@ -72,6 +72,30 @@ def cpu_baseline(L=12, tau=1e-6):
     }
 
 
+def bsr_diff_frobenius(A, B):
+    """||A - B||_F of two symmetric upper-BSR device matrices (blocks matched
+    by (I, J); off-diagonal blocks count twice for their mirrors)."""
+    import torch
+
+    def keys(M):
+        rows = torch.repeat_interleave(torch.arange(M.nbr, device=M.device), torch.diff(M.row_ptr))
+        return rows, M.col_idx.long(), rows * M.nbr + M.col_idx.long()
+
+    ra, ca, ka = keys(A)
+    rb, cb, kb = keys(B)
+    pos = torch.searchsorted(kb, ka).clamp(max=max(kb.numel() - 1, 0))
+    hit = kb[pos] == ka
+    wa = torch.where(ra == ca, 1.0, 2.0).double()
+    wb = torch.where(rb == cb, 1.0, 2.0).double()
+    d = A.val.clone()
+    d[hit] -= B.val[pos[hit]]
+    tot = (wa * (d * d).sum(dim=(1, 2))).sum()
+    used = torch.zeros(kb.numel(), dtype=torch.bool, device=kb.device)
+    used[pos[hit]] = True
+    tot += (wb[~used] * (B.val[~used] ** 2).sum(dim=(1, 2))).sum()
+    return float(tot.sqrt())
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -157,6 +181,14 @@ def main():
     ms = 1e3 * total / args.steps
     value = sum(flops) / sum(times) / 1e12
     achieved = sum(flops) / sum(ksq) / 1e12
+    mixed = {}
+    if prec != "fp64":
+        ref = sp2.density(F, no, lmin, lmax, hub, llb, precision="fp64", **opts)
+        err = bsr_diff_frobenius(res.D, ref.D)
+        mixed = {"err_vs_fp64_D": err, "fp64_time_to_D_s": ref.time_s, "speedup_vs_fp64": ref.time_s / (sum(times) / len(times)),
+                 "switch_iter": res.switch_iter, "fp64_n_iter": ref.n_iter}
+        log(f"mixed {prec}: ||D - D_fp64||_F = {err:.3e}, FP64 run {ref.time_s:.3f} s, speedup "
+            f"{mixed['speedup_vs_fp64']:.2f}x, switch at {res.switch_iter}")
     n, rp, ci, v = res.D.to_host()
     diag = np.array([np.trace(v[b]) for b in range(len(ci)) if ci[b] == np.searchsorted(rp, b, side="right") - 1])
     trD = float(diag.sum())
@@ -183,7 +215,7 @@ def main():
             "alg_tflop_per_step": round(res.alg_flops / 1e12, 3),
         },
         "checks": {"trace_err": abs(trD - no), "e_n": float(res.iters["e"][-1]),
-                   "homo_est": res.homo_est, "lumo_est": res.lumo_est},
+                   "homo_est": res.homo_est, "lumo_est": res.lumo_est, **mixed},
         "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK[prec], "unit": "TFLOP/s",
                      "frac": round(achieved / PEAK[prec], 4), "traffic": None,
                      "kernel": "k_square (MFMA block-sparse symmetric square + fused epilogue)"},

@@ -207,6 +207,29 @@ int sp2_replay(sp2_ctx *ctx, const sp2_tape *tape, const sp2_bsr *F, sp2_bsr **D
 /* Tape facts: number of iterations, checkpoints held, bytes held on the device. */
 int sp2_tape_info(const sp2_tape *tape, int32_t *n_iter, int32_t *n_checkpoints, int64_t *device_bytes);
 
+/* ---- host scalar control (no GPU involved) ------------------------------ */
+
+/* Step 1 schedule from homo/lumo bounds (section "Density matrix
+ * construction"): polynomial sequence p_i, scale-and-fold parameters alpha_i
+ * (alpha_i = 1 for SP2, accel = 0), the bound images l_i (unoccupied images in
+ * [0, l_i]) and q_i (occupied images in [1 - q_i, 1]), the gap bounds
+ * xi_i = 1 - l_i - q_i and thresholds tau_i of eq. (tau_trunc) (or tau_fixed
+ * when > 0).  Output arrays are host arrays of length n_max_cap + 1 (entry 0 of
+ * p and alpha is unused: -1 and 1); n_max and n_min are returned.  The same
+ * formulas drive sp2_density. */
+int sp2_schedule(double lmin, double lmax, double homo_ub, double lumo_lb, int accel, double gamma, double tau_fixed,
+                 int n_max_cap, int32_t *n_max, int32_t *n_min, int32_t *p, double *alpha, double *l, double *q,
+                 double *xi, double *tau);
+
+/* Step 3 homo/lumo estimates from e_i = ||X~_i - X~_i^2||_F and tr X~_i,
+ * i = 0..n, of a finished run with polynomials p_i and alpha_i.  bounds_mode
+ * = 1: the run used homo/lumo bounds and l, q are its schedule arrays;
+ * bounds_mode = 0: trace-correcting run (l, q unused).  N = matrix size.
+ * Writes NaN when no iteration qualifies.  Host arrays of length n + 1. */
+int sp2_homo_lumo(int bounds_mode, int n, const double *e, const double *trace, const int32_t *p, const double *alpha,
+                  const double *l, const double *q, double lmin, double lmax, int64_t N, int64_t n_occ,
+                  double *homo_ub, double *lumo_lb);
+
 /* ---- single steps of the hot path (kernel-level entry points) ---------- */
 
 /* One square of Algorithm 2 on an upper-BSR X: S = X^2 on the block pattern

@@ -24,7 +24,8 @@ STOP_CRITERION, STOP_IDEMPOTENCY, STOP_NMAX = 1, 2, 3
 EXPORTS = [
     "sp2_version", "sp2_options_default", "sp2_create", "sp2_destroy", "sp2_set_allocator", "sp2_trim",
     "sp2_last_error", "sp2_gershgorin", "sp2_density", "sp2_vjp", "sp2_jvp", "sp2_replay", "sp2_tape_info",
-    "sp2_square_step", "sp2_truncate", "sp2_bsr_copy", "sp2_bsr_free", "sp2_tape_free",
+    "sp2_square_step", "sp2_truncate", "sp2_bsr_copy", "sp2_bsr_free", "sp2_tape_free", "sp2_schedule",
+    "sp2_homo_lumo",
 ]
 
 
@@ -145,6 +146,13 @@ def load(path: str = LIB_PATH):
     lib.sp2_bsr_copy.argtypes = [C.c_void_p, P(sp2_bsr), C.c_void_p, C.c_void_p, C.c_void_p]
     lib.sp2_bsr_free.restype = None
     lib.sp2_bsr_free.argtypes = [C.c_void_p, P(sp2_bsr)]
+    DP, IP = P(C.c_double), P(C.c_int32)
+    lib.sp2_schedule.restype = C.c_int
+    lib.sp2_schedule.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double, C.c_int, C.c_double, C.c_double,
+                                 C.c_int, IP, IP, IP, DP, DP, DP, DP, DP]
+    lib.sp2_homo_lumo.restype = C.c_int
+    lib.sp2_homo_lumo.argtypes = [C.c_int, C.c_int, DP, DP, IP, DP, DP, DP, C.c_double, C.c_double, C.c_int64,
+                                  C.c_int64, DP, DP]
     lib.sp2_tape_free.restype = None
     lib.sp2_tape_free.argtypes = [C.c_void_p, C.c_void_p]
     _lib = lib

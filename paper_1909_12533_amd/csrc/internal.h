@@ -175,6 +175,7 @@ struct TileArgs {
   const int32_t *oidx;     // nbr x nbr: pattern position of output block (I, J), or -1
   const int32_t *tiles;    // ntiles pairs (TI, TJ), TI <= TJ in units of 2 blocks
   int64_t ntiles;
+  int64_t xcd_chunk;       // tiles per XCD: workgroup b runs tile (b % 8) * xcd_chunk + b / 8
   void *opool;             // output block at its pattern position
   int oprec;
   double ca, cb, cc;
@@ -183,6 +184,7 @@ struct TileArgs {
 };
 int64_t build_tiles(Ctx &c, const int32_t *oidx, int nbr, Buf &tiles);
 void launch_square_tile(Ctx &c, int mode, const TileArgs &a);
+void launch_square_tile_bf16x3(Ctx &c, const TileArgs &a);  // kernels_bf16x3.hip
 
 // anticommutator products for the adjoint (kernels_square.hip)
 struct AntiArgs {

@@ -86,19 +86,14 @@ __device__ inline void mma_dispatch(typename MF<T>::acc_t (&acc)[4][4], const T 
     mma_full<T, true, true>(acc, As, Bs);
 }
 
-__device__ inline double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
 
 template <typename T, typename TO>
 __global__ __launch_bounds__(TPB, 1) void k_square_tile(TileArgs a) {
   constexpr int LD = MF<T>::LD;
   __shared__ __align__(16) T As[2][64 * LD];
   __shared__ __align__(16) T Bs[2][64 * LD];
-  const int64_t t = blockIdx.x;
-  if (t >= a.ntiles) return;
+  const int64_t t = xcd_tile(a);
+  if (t < 0) return;
   const int nbr = a.nbr, W = a.W;
   const int I0 = 2 * __builtin_amdgcn_readfirstlane(a.tiles[2 * t]);
   const int J0 = 2 * __builtin_amdgcn_readfirstlane(a.tiles[2 * t + 1]);
@@ -191,57 +186,33 @@ __global__ __launch_bounds__(TPB, 1) void k_square_tile(TileArgs a) {
 #undef SP2_LOAD_BLOCK
   if (pos < 0) return;
 
-  // epilogue: X_next = ca I + cb X + cc S on block (I, J); per-block partials
-  const int l16 = lane & 15, g = lane >> 4;
-  const int32_t sx = a.idxmap[(int64_t)I * nbr + J];
-  const T *xb = sx >= 0 ? xp + (int64_t)sx * BB : nullptr;
-  TO *ob = static_cast<TO *>(a.opool) + (int64_t)pos * BB;
-  double e2 = 0.0, tx = 0.0, ts = 0.0, nr = 0.0;
-#pragma unroll
-  for (int m = 0; m < 4; ++m)
-#pragma unroll
-    for (int n = 0; n < 4; ++n)
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int r = 16 * m + MF<T>::row(g, q);
-        const int c = 16 * n + l16;
-        const double s = (double)acc[m][n][q];
-        const double x = xb ? (double)xb[r * 64 + c] : 0.0;
-        const bool dg = (I == J) && (r == c);
-        const bool real_dg = dg && ((int64_t)I * B + r < a.n);
-        const double o = a.cc * s + a.cb * x + (real_dg ? a.ca : 0.0);
-        const TO ov = (TO)o;
-        ob[r * 64 + c] = ov;
-        const double od = (double)ov;
-        nr += od * od;
-        const double df = x - s;
-        e2 += df * df;
-        if (dg) {
-          tx += x;
-          ts += s;
-        }
-      }
-  e2 = wave_sum(e2);
-  tx = wave_sum(tx);
-  ts = wave_sum(ts);
-  nr = wave_sum(nr);
-  if (lane == 0) {
-    double *p = a.parts + (int64_t)pos * NPART;
-    p[0] = (I == J) ? e2 : 2.0 * e2;
-    p[1] = tx;
-    p[2] = ts;
-    p[3] = nr;
-    p[4] = (double)nk;
-  }
+  square_epilogue<T, TO>(acc, a, I, J, pos, xp, nk, [](int g, int q) { return MF<T>::row(g, q); });
+}
+
+// Tile order: super-tiles of ST x ST tiles (2 ST x 2 ST output blocks) in
+// row-major order, tiles row-major inside a super-tile.  Linear id
+// ((STI * nst + STJ) * ST + ti) * ST + tj with TI = STI * ST + ti,
+// TJ = STJ * ST + tj.
+constexpr int ST = 4;
+
+__device__ inline bool tile_of(int64_t id, int ntr, int nst, int &TI, int &TJ) {
+  const int tj = (int)(id % ST);
+  const int64_t r1 = id / ST;
+  const int ti = (int)(r1 % ST);
+  const int64_t r2 = r1 / ST;
+  const int STJ = (int)(r2 % nst), STI = (int)(r2 / nst);
+  TI = STI * ST + ti;
+  TJ = STJ * ST + tj;
+  return TI < ntr && TJ < ntr && TI <= TJ;
 }
 
 // flags of 2 x 2 output tiles holding at least one output block
-__global__ void k_tile_flags(const int32_t *oidx, int nbr, int ntr, int64_t *flag) {
+__global__ void k_tile_flags(const int32_t *oidx, int nbr, int ntr, int nst, int64_t nid, int64_t *flag) {
   const int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (id >= (int64_t)ntr * ntr) return;
-  const int TI = (int)(id / ntr), TJ = (int)(id % ntr);
+  if (id >= nid) return;
+  int TI, TJ;
   int64_t f = 0;
-  if (TI <= TJ) {
+  if (tile_of(id, ntr, nst, TI, TJ)) {
     for (int a = 0; a < 2; ++a)
       for (int b = 0; b < 2; ++b) {
         const int I = 2 * TI + a, J = 2 * TJ + b;
@@ -251,35 +222,38 @@ __global__ void k_tile_flags(const int32_t *oidx, int nbr, int ntr, int64_t *fla
   flag[id] = f;
 }
 
-__global__ void k_tile_write(const int64_t *flag, const int64_t *pos, int ntr, int32_t *tiles) {
+__global__ void k_tile_write(const int64_t *flag, const int64_t *pos, int ntr, int nst, int64_t nid, int32_t *tiles) {
   const int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (id >= (int64_t)ntr * ntr || !flag[id]) return;
+  if (id >= nid || !flag[id]) return;
+  int TI, TJ;
+  tile_of(id, ntr, nst, TI, TJ);
   const int64_t o = pos[id];
-  tiles[2 * o] = (int32_t)(id / ntr);
-  tiles[2 * o + 1] = (int32_t)(id % ntr);
+  tiles[2 * o] = TI;
+  tiles[2 * o + 1] = TJ;
 }
 
 }  // namespace
 
 int64_t build_tiles(Ctx &c, const int32_t *oidx, int nbr, Buf &tiles) {
   const int ntr = (nbr + 1) / 2;
-  const int64_t n = (int64_t)ntr * ntr;
-  Buf flag = c.alloc(sizeof(int64_t) * n), pos = c.alloc(sizeof(int64_t) * (n + 1));
-  k_tile_flags<<<(unsigned)((n + TPB - 1) / TPB), TPB, 0, c.stream>>>(oidx, nbr, ntr, flag.as<int64_t>());
+  const int nst = (ntr + ST - 1) / ST;
+  const int64_t nid = (int64_t)nst * nst * ST * ST;
+  Buf flag = c.alloc(sizeof(int64_t) * nid), pos = c.alloc(sizeof(int64_t) * (nid + 1));
+  k_tile_flags<<<(unsigned)((nid + TPB - 1) / TPB), TPB, 0, c.stream>>>(oidx, nbr, ntr, nst, nid, flag.as<int64_t>());
   SP2_LAUNCH_CHECK();
-  scan_exclusive_i64(c, flag.as<int64_t>(), pos.as<int64_t>(), n);
+  scan_exclusive_i64(c, flag.as<int64_t>(), pos.as<int64_t>(), nid);
   int64_t nt = 0;
-  c.d2h(&nt, pos.as<int64_t>() + n, sizeof(int64_t));
+  c.d2h(&nt, pos.as<int64_t>() + nid, sizeof(int64_t));
   tiles = c.alloc(sizeof(int32_t) * 2 * (nt > 0 ? nt : 1));
-  k_tile_write<<<(unsigned)((n + TPB - 1) / TPB), TPB, 0, c.stream>>>(flag.as<int64_t>(), pos.as<int64_t>(), ntr,
-                                                                      tiles.as<int32_t>());
+  k_tile_write<<<(unsigned)((nid + TPB - 1) / TPB), TPB, 0, c.stream>>>(flag.as<int64_t>(), pos.as<int64_t>(), ntr, nst,
+                                                                        nid, tiles.as<int32_t>());
   SP2_LAUNCH_CHECK();
   return nt;
 }
 
 void launch_square_tile(Ctx &c, int mode, const TileArgs &a) {
   if (a.ntiles <= 0) return;
-  const unsigned g = (unsigned)a.ntiles;
+  const unsigned g = (unsigned)(8 * a.xcd_chunk);
   if (mode == M_F64) {
     if (a.xprec != P64 || a.oprec != P64) fail(SP2_ERR_INVALID_ARG, "FP64 square needs FP64 pools");
     k_square_tile<double, double><<<g, TPB, 0, c.stream>>>(a);
@@ -289,8 +263,11 @@ void launch_square_tile(Ctx &c, int mode, const TileArgs &a) {
       k_square_tile<float, float><<<g, TPB, 0, c.stream>>>(a);
     else
       k_square_tile<float, double><<<g, TPB, 0, c.stream>>>(a);
+  } else if (mode == M_BF16X3) {
+    launch_square_tile_bf16x3(c, a);
+    return;
   } else {
-    fail(SP2_ERR_INVALID_ARG, "square mode not available");
+    fail(SP2_ERR_INVALID_ARG, "unknown square mode");
   }
   SP2_LAUNCH_CHECK();
 }

@@ -199,5 +199,75 @@ __device__ inline int accumulate(typename MF<T>::acc_t (&acc)[2][2], Src<T> A, c
   return nk;
 }
 
+
+// XCD-aware tile index: workgroups are dispatched round-robin over the 8
+// XCDs (each with its own L2), so XCD x runs workgroups x, x + 8, ...; giving
+// it the contiguous chunk [x * chunk, (x + 1) * chunk) of the (super-tile
+// ordered) tile list keeps tiles that share operand panels on the same L2.
+// Returns -1 for the padding workgroups of the last chunk.
+__device__ inline int64_t xcd_tile(const TileArgs &a) {
+  const int64_t b = blockIdx.x;
+  const int64_t t = (b % 8) * a.xcd_chunk + b / 8;
+  return t < a.ntiles ? t : -1;
+}
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Epilogue of the square for the 64 x 64 output block (I, J) held by one wave
+// in 4 x 4 MFMA 16 x 16 accumulator tiles: X_next = ca I + cb X + cc S is
+// written at pattern position pos, and the block's partial sums (e^2 weighted
+// by 2 off the diagonal, tr X, tr S, ||X_next||^2, #K) go to parts.
+// rowf(g, v) is the tile row of accumulator element v of lane group g.
+template <typename T, typename TO, typename ACC, typename RowF>
+__device__ inline void square_epilogue(const ACC (&acc)[4][4], const TileArgs &a, int I, int J, int pos, const T *xp,
+                                       int nk, RowF rowf) {
+  const int lane = threadIdx.x & 63;
+  const int l16 = lane & 15, g = lane >> 4;
+  const int32_t sx = a.idxmap[(int64_t)I * a.nbr + J];
+  const T *xb = sx >= 0 ? xp + (int64_t)sx * BB : nullptr;
+  TO *ob = static_cast<TO *>(a.opool) + (int64_t)pos * BB;
+  double e2 = 0.0, tx = 0.0, ts = 0.0, nr = 0.0;
+#pragma unroll
+  for (int m = 0; m < 4; ++m)
+#pragma unroll
+    for (int n = 0; n < 4; ++n)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int r = 16 * m + rowf(g, q);
+        const int c = 16 * n + l16;
+        const double s = (double)acc[m][n][q];
+        const double x = xb ? (double)xb[r * 64 + c] : 0.0;
+        const bool dg = (I == J) && (r == c);
+        const bool real_dg = dg && ((int64_t)I * B + r < a.n);
+        const double o = a.cc * s + a.cb * x + (real_dg ? a.ca : 0.0);
+        const TO ov = (TO)o;
+        ob[r * 64 + c] = ov;
+        const double od = (double)ov;
+        nr += od * od;
+        const double df = x - s;
+        e2 += df * df;
+        if (dg) {
+          tx += x;
+          ts += s;
+        }
+      }
+  e2 = wave_sum(e2);
+  tx = wave_sum(tx);
+  ts = wave_sum(ts);
+  nr = wave_sum(nr);
+  if (lane == 0) {
+    double *p = a.parts + (int64_t)pos * NPART;
+    p[0] = (I == J) ? e2 : 2.0 * e2;
+    p[1] = tx;
+    p[2] = ts;
+    p[3] = nr;
+    p[4] = (double)nk;
+  }
+}
+
 }  // namespace dev
 }  // namespace sp2

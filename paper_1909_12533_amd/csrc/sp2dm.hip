@@ -12,6 +12,7 @@
 // The only device -> host traffic per iteration is a handful of scalars and
 // the sizes needed to allocate the next pattern.
 #include <chrono>
+#include <cstdlib>
 #include <cmath>
 #include <cstdio>
 #include <limits>
@@ -26,6 +27,15 @@ namespace sp2 {
 namespace {
 
 constexpr double NaN = std::numeric_limits<double>::quiet_NaN();
+
+// per-iteration progress on stderr when SP2_VERBOSE is set (long runs)
+bool verbose() {
+  static const bool v = [] {
+    const char *s = std::getenv("SP2_VERBOSE");
+    return s && *s && *s != '0';
+  }();
+  return v;
+}
 
 Buf view(const void *p, size_t bytes) {
   Buf b;
@@ -248,6 +258,7 @@ SquareOut square_step(Ctx &c, const DMat &X, const Maps &m, int mode, int oprec,
   ta.oidx = om.idxmap.as<int32_t>();
   ta.tiles = tiles.as<int32_t>();
   ta.ntiles = ntiles;
+  ta.xcd_chunk = (ntiles + 7) / 8;
   ta.opool = r.next.pool->vals.p;
   ta.oprec = oprec;
   ta.ca = ca;
@@ -603,6 +614,10 @@ int run_density(Ctx &c, const sp2_bsr *Fin, int64_t n_occ, double lmin, double l
     X = std::move(Xn);
     c.sync();
     itime.push_back(std::chrono::duration<double>(std::chrono::steady_clock::now() - t_it).count());
+    if (verbose())
+      std::fprintf(stderr, "[sp2] iter %d p=%d alpha=%.6f nnzb=%lld e=%.3e t=%.3e square %.1f ms (%.2f TFLOP/s)%s\n", i,
+                   p[i], alph[i], (long long)nnzbv[i], e[i], t[i], 1e3 * ksq[i],
+                   ksq[i] > 0.0 ? iflops[i] / ksq[i] / 1e12 : 0.0, mode == M_F64 ? "" : " low precision");
   }
 
   // ---- Step 3 and outputs ---------------------------------------------------------
@@ -939,6 +954,52 @@ int sp2_tape_info(const sp2_tape *tape, int32_t *n_iter, int32_t *n_checkpoints,
   if (n_iter) *n_iter = tape->n_iter;
   if (n_checkpoints) *n_checkpoints = tape->n_ckpt;
   if (device_bytes) *device_bytes = tape->bytes;
+  return SP2_OK;
+}
+
+int sp2_schedule(double lmin, double lmax, double homo_ub, double lumo_lb, int accel, double gamma, double tau_fixed,
+                 int n_max_cap, int32_t *n_max, int32_t *n_min, int32_t *p, double *alpha, double *l, double *q,
+                 double *xi, double *tau) {
+  if (!(std::isfinite(lmin) && std::isfinite(lmax) && lmin < lmax)) return SP2_ERR_INVALID_ARG;
+  if (!(lmin <= homo_ub && homo_ub < lumo_lb && lumo_lb <= lmax)) return SP2_ERR_BAD_BOUNDS;
+  if (n_max_cap < 1 || n_max_cap > 1000 || !(gamma >= 0.0) || !(tau_fixed >= 0.0)) return SP2_ERR_INVALID_ARG;
+  try {
+    const Sched s = make_schedule(lmin, lmax, homo_ub, lumo_lb, accel != 0, gamma, tau_fixed, n_max_cap);
+    if (n_max) *n_max = s.n_max;
+    if (n_min) *n_min = s.n_min;
+    for (int i = 0; i <= s.n_max; ++i) {
+      if (p) p[i] = s.p[i];
+      if (alpha) alpha[i] = s.alpha[i];
+      if (l) l[i] = s.l[i];
+      if (q) q[i] = s.q[i];
+      if (xi) xi[i] = s.xi[i];
+      if (tau) tau[i] = s.tau[i];
+    }
+  } catch (...) {
+    return SP2_ERR_OOM;
+  }
+  return SP2_OK;
+}
+
+int sp2_homo_lumo(int bounds_mode, int n, const double *e, const double *trace, const int32_t *p, const double *alpha,
+                  const double *l, const double *q, double lmin, double lmax, int64_t N, int64_t n_occ,
+                  double *homo_ub, double *lumo_lb) {
+  if (n < 0 || !e || !p || !alpha || !homo_ub || !lumo_lb || !(lmin < lmax)) return SP2_ERR_INVALID_ARG;
+  if (bounds_mode ? (!l || !q) : !trace) return SP2_ERR_INVALID_ARG;
+  try {
+    Sched s;
+    s.bounds = bounds_mode != 0;
+    if (s.bounds) {
+      s.l.assign(l, l + n + 1);
+      s.q.assign(q, q + n + 1);
+    }
+    std::vector<double> ev(e, e + n + 1), tv(n + 1, 0.0), av(alpha, alpha + n + 1);
+    if (trace) tv.assign(trace, trace + n + 1);
+    std::vector<int> pv(p, p + n + 1);
+    homo_lumo(s, ev, tv, pv, av, n, lmin, lmax, N, n_occ, *homo_ub, *lumo_lb);
+  } catch (...) {
+    return SP2_ERR_OOM;
+  }
   return SP2_OK;
 }
 

@@ -92,3 +92,34 @@ def test_vjp_daleckii_krein_dense(gpu_lib):
     g = to_dense(r.tape.vjp(sp2.BsrMatrix.from_host(dense_to_bsr(W))))
     g_dk = O.daleckii_krein_gradient(Fd, 128, W)
     assert rel(g, g_dk) <= 1e-8
+
+
+def test_autograd_function_matches_finite_differences(gpu_lib):
+    """torch.autograd through the library's VJP: the directional derivative of
+    L = sum(g * D_val) along dF equals the central difference of the frozen map."""
+    import torch
+
+    from paper_1909_12533_amd.autograd import density_matrix
+
+    sp2 = gpu_lib
+    Fh, info = lattice_fock(6, seed=0)
+    no = info["n_occ"]
+    lmin, lmax = O.gershgorin_bounds(bsr_to_dense(Fh))
+    F = sp2.BsrMatrix.from_host(Fh)
+    Fv = F.val.clone().requires_grad_(True)
+    kw = dict(accel=True, trunc_norm="frobinf", tau_fixed=1e-2, coarse_bs=128)
+    Dv, rp, ci = density_matrix(Fv, F.row_ptr, F.col_idx, F.n, no, lmin, lmax, -0.37, 0.34, **kw)
+    gen = torch.Generator(device="cpu").manual_seed(5)
+    g = torch.randn(Dv.shape, generator=gen, dtype=torch.float64).to(Dv.device)
+    L = (g * Dv).sum()
+    L.backward()
+    dFh = random_sym_on_pattern(Fh, 1e-3, seed=1)
+    dF = torch.as_tensor(dFh.val).to(Dv.device)
+    lhs = float((Fv.grad * dF).sum())
+    tape = Dv.grad_fn.tape
+    h = 1e-5
+    Dp = tape.replay(sp2.BsrMatrix(F.n, F.row_ptr, F.col_idx, (F.val + h * dF).contiguous()))
+    Dm = tape.replay(sp2.BsrMatrix(F.n, F.row_ptr, F.col_idx, (F.val - h * dF).contiguous()))
+    assert torch.equal(Dp.row_ptr, rp) and torch.equal(Dp.col_idx, ci)
+    rhs = float((g * (Dp.val - Dm.val)).sum()) / (2 * h)
+    assert lhs == pytest.approx(rhs, rel=1e-6)

@@ -143,3 +143,21 @@ def test_mixed_fp32_reports_error(gpu_lib):
     print(f"mixed fp32 vs fp64: ||dD||_F = {err:.3e}, n = {r32.n_iter} vs {r64.n_iter}")
     assert err <= 1e-3
     assert abs(np.trace(D32) - no) <= 1e-6
+
+
+def test_mixed_bf16x3_reports_error(gpu_lib):
+    sp2 = gpu_lib
+    Fh, info = lattice_fock(8, seed=0)
+    Fd = bsr_to_dense(Fh)
+    no = info["n_occ"]
+    lmin, lmax = O.gershgorin_bounds(Fd)
+    F = sp2.BsrMatrix.from_host(Fh)
+    r64 = sp2.density(F, no, lmin, lmax, -0.31, 0.33, trunc_norm="frobinf", tau_fixed=1e-6, coarse_bs=512)
+    rb = sp2.density(F, no, lmin, lmax, -0.31, 0.33, trunc_norm="frobinf", tau_fixed=1e-6, coarse_bs=512,
+                     precision="bf16x3")
+    assert rb.switch_iter >= 1
+    assert set(rb.iters["precision"][: rb.switch_iter]) == {2}
+    err = np.linalg.norm(to_dense(rb.D) - to_dense(r64.D))
+    print(f"mixed bf16x3 vs fp64: ||dD||_F = {err:.3e}, n = {rb.n_iter} vs {r64.n_iter}, switch {rb.switch_iter}")
+    assert err <= 5e-2
+    assert abs(np.trace(to_dense(rb.D)) - no) <= 1e-6

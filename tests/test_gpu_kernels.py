@@ -137,3 +137,23 @@ def test_deterministic_square(gpu_lib):
     Y2, s2 = sp2.square_step(X, 0.1, 0.2, 0.3)
     assert s1 == s2
     assert bool((Y1.val == Y2.val).all())
+
+
+@pytest.mark.parametrize("n,dens,seed", CASES[1:3])
+def test_square_step_bf16x3(gpu_lib, n, dens, seed):
+    """hi*hi + hi*lo + lo*hi with x = hi + lo + d, |lo| <= 2^-8 |x|,
+    |d| <= 2^-16 |x|: each product is off by at most 3 * 2^-16 |x||y|, plus FP32
+    rounding of the inputs and of the accumulation."""
+    sp2 = gpu_lib
+    Xh = random_sym_bsr(n, dens, seed=seed, std=0.1)
+    X = sp2.BsrMatrix.from_host(Xh)
+    Y, sums = sp2.square_step(X, 0.0, 2.0, -1.0, "bf16x3")
+    Xd, S, ref, MS, Mst = _oracle_square(Xh, n, 0.0, 2.0, -1.0)
+    assert np.array_equal(upper_mask(Y), np.triu(MS))
+    Xa = np.abs(Xd)
+    u = 2.0 ** -24
+    bound = 3 * 2.0 ** -16 * (Xa @ Xa) + 4 * u * (2 * Xa + (n + 2) * (Xa @ Xa)) + 1e-30
+    err = np.abs(to_dense(Y) - ref)
+    assert np.all(err <= bound)
+    # and it is genuinely better than a plain bf16 product (error ~2^-8)
+    assert np.max(err / (Xa @ Xa + 1e-30)) < 2.0 ** -12
