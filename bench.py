@@ -106,6 +106,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="copy a buffer of this size once before timing (reference for HBM traffic counters)")
+    ap.add_argument("--correct", type=int, default=None,
+                    help="subspace-correction rounds (default: 0 for fp64, 1 for fp32, 2 for bf16x3)")
+    ap.add_argument("--corr-tol", type=float, default=None,
+                    help="Frobenius budget for dropping blocks of the correction's intermediates (library default)")
+    ap.add_argument("--switch-tol", type=float, default=None,
+                    help="FP64 tail once ||X - X^2||_F < this (default: 0 with the correction, else 1e-3)")
     ap.add_argument("--bounds", default=None,
                     help="homo_ub,lumo_lb known in advance (e.g. from a previous SCF cycle): skips the first run")
     args = ap.parse_args()
@@ -150,8 +156,14 @@ def main():
         log(f"calibration copy: {nb} bytes read, {nb} bytes written")
         del src, dst
 
+    correct = args.correct if args.correct is not None else {"fp64": 0, "fp32": 1, "bf16x3": 2}[prec]
+    switch_tol = args.switch_tol if args.switch_tol is not None else (0.0 if correct else 1e-3)
+    mopts = dict(precision=prec, correct=correct, switch_tol=switch_tol) if prec != "fp64" else dict(correct=correct)
+    if args.corr_tol is not None:
+        mopts["corr_tol"] = args.corr_tol
+
     def step():
-        return sp2.density(F, no, lmin, lmax, hub, llb, precision=prec, **opts)
+        return sp2.density(F, no, lmin, lmax, hub, llb, **mopts, **opts)
 
     for _ in range(args.warmup):
         r = step()
@@ -180,15 +192,20 @@ def main():
     total = time.perf_counter() - t_all
     ms = 1e3 * total / args.steps
     value = sum(flops) / sum(times) / 1e12
-    achieved = sum(flops) / sum(ksq) / 1e12
+    # roofline of the dominant kernel: the expansion's squares in the run's
+    # bulk precision (code 0 FP64, 1 FP32, 2 BF16x3), flops / HIP-event time
+    code = {"fp64": 0, "fp32": 1, "bf16x3": 2}[prec]
+    sel = res.iters["precision"] == code
+    achieved = float(res.iters["iter_flops"][sel].sum() / res.iters["square_time_s"][sel].sum() / 1e12)
     mixed = {}
     if prec != "fp64":
         ref = sp2.density(F, no, lmin, lmax, hub, llb, precision="fp64", **opts)
         err = bsr_diff_frobenius(res.D, ref.D)
         mixed = {"err_vs_fp64_D": err, "fp64_time_to_D_s": ref.time_s, "speedup_vs_fp64": ref.time_s / (sum(times) / len(times)),
-                 "switch_iter": res.switch_iter, "fp64_n_iter": ref.n_iter}
+                 "switch_iter": res.switch_iter, "switch_tol": switch_tol, "fp64_n_iter": ref.n_iter,
+                 "correction": res.correction}
         log(f"mixed {prec}: ||D - D_fp64||_F = {err:.3e}, FP64 run {ref.time_s:.3f} s, speedup "
-            f"{mixed['speedup_vs_fp64']:.2f}x, switch at {res.switch_iter}")
+            f"{mixed['speedup_vs_fp64']:.2f}x, switch at {res.switch_iter}, correction {res.correction}")
     n, rp, ci, v = res.D.to_host()
     diag = np.array([np.trace(v[b]) for b in range(len(ci)) if ci[b] == np.searchsorted(rp, b, side="right") - 1])
     trD = float(diag.sum())
@@ -208,7 +225,8 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": f"tight-binding Fock {L}x{L}x{L} lattice x 4 basis fns (N={info['n']}), "
-                        f"{'FP64 SP2ACC' if prec == 'fp64' else prec + ' mixed SP2ACC'}, 64x64 blocks, "
+                        f"{'FP64 SP2ACC' if prec == 'fp64' else prec + ' mixed SP2ACC'}"
+                        f"{' + FP64 subspace correction' if correct else ''}, 64x64 blocks, "
                         f"tau={tau} Frob-Inf(4096), Gershgorin bounds, homo/lumo from a trace-correcting run",
             "n": info["n"], "n_occ": no, "tau": tau, "precision": prec,
             "n_iter": res.n_iter, "stop": res.stop_reason, "max_nnzb": res.max_nnzb,

@@ -107,6 +107,11 @@ typedef struct {
   double idem_stop;     /* > 0: also stop when e_i <= idem_stop */
   int32_t record_tape;  /* 1: keep the masks and checkpoints needed by vjp / jvp / replay */
   int32_t n_checkpoints;/* number of X~_i checkpoints in the tape; 0 = ceil(sqrt(n)) */
+  int32_t correct;      /* rounds of the FP64 occupied-subspace correction after the expansion (0 = none);
+                           see "Subspace correction" below */
+  int32_t corr_purify;  /* FP64 purification squares after each correction round (>= 1; default 2) */
+  double corr_tol;      /* Frobenius budget for dropping small blocks of every intermediate of the
+                           correction (0 = default 1e-9) */
 } sp2_options;
 
 /* Per-run statistics.  Arrays are HOST arrays owned by the caller, each of
@@ -138,6 +143,15 @@ typedef struct {
   int64_t *nnzb;        /* stored upper blocks of X~_i */
   double *square_time_s;   /* device time of the MFMA square of X~_i (HIP events on the context stream) */
   double square_time_total_s; /* sum of square_time_s over the run */
+  /* subspace correction (zero when opt->correct == 0) */
+  int32_t corr_rounds;
+  double corr_time_s;      /* wall time of all rounds (part of time_s) */
+  double corr_flops;       /* algorithmic flops of their block products (part of alg_flops) */
+  double corr_delta_norm;  /* ||Delta||_F of the last round, Delta = [D, [D, F]] */
+  double corr_step_norm;   /* ||dD||_F of the last round (the first-order correction) */
+  double corr_e_last;      /* ||P - P^2||_F of the input P of the last purification square */
+  int64_t corr_max_nnzb;   /* largest pattern among the correction's intermediates */
+  int64_t seq_bytes;       /* device bytes of the stored X~_i sequence the correction replays */
 } sp2_stats;
 
 typedef void *(*sp2_alloc_fn)(size_t bytes, void *user);
@@ -148,7 +162,7 @@ const char *sp2_version(void);
 
 /* Fill *opt with the defaults: SP2ACC, FP64, switch_tol 1e-3, Frob-Inf,
  * n_max_cap 100, coarse_bs 4096, gamma 1e-3, tau_fixed 0, idem_stop 0,
- * no tape. */
+ * no tape, no subspace correction (corr_purify 2, corr_tol 1e-9). */
 void sp2_options_default(sp2_options *opt);
 
 /* Create a context on HIP device `device` issuing all work on `hip_stream`
@@ -173,6 +187,29 @@ const char *sp2_last_error(const sp2_ctx *ctx);
  * lambda_min <= lambda_1 and lambda_max >= lambda_N). */
 int sp2_gershgorin(sp2_ctx *ctx, const sp2_bsr *F, double *lmin, double *lmax);
 
+/* Subspace correction (opt->correct > 0).  Squares in low precision perturb
+ * the occupied subspace, and later iterations keep such a perturbation
+ * instead of removing it (section "Error control": an error in the occupied
+ * subspace is not recovered); an FP64 tail restores idempotency and trace but
+ * not the subspace.  After the expansion, each round takes the current
+ * D (a near-projector) and
+ *   Delta = [D, [D, F]] = D F (I - D) + (I - D) F D          (FP64 commutator
+ *           C = [D, F] first: C is small, so [D, C] may use the low precision)
+ *   dD    = J Delta, J the derivative of the expansion's map F -> D
+ *           (dX~_0 = -Delta / (lmax - lmin), dX~_i = b_i dX~_{i-1}
+ *           + c_i (X~_{i-1} dX~_{i-1} + dX~_{i-1} X~_{i-1}) along the stored
+ *           X~_0 .. X~_{n-1} with the run's polynomials)
+ *   D     <- purified (D + dD): corr_purify FP64 steps X^2, 2X - X^2, ...
+ * In the eigenbasis of F the occupied-virtual part of Delta is
+ * (lambda_v - lambda_o) E_ov for D = theta + E, and J divides that part by
+ * (lambda_o - lambda_v), so D + dD removes E to first order; the residual is
+ * O(||E||^2 / gap).  Blocks of C, Delta and every dX~_i are dropped while the
+ * Frobenius norm of the dropped part stays within corr_tol.  With
+ * switch_tol = 0 the expansion runs in the low precision to its stopping
+ * criterion (evaluated on the low-precision e_i) and the purification replaces
+ * the FP64 tail.  The X~_i are kept on the device for the correction
+ * (stats->seq_bytes). */
+
 /* Density matrix by SP2 / SP2ACC (Steps 1-3, Algorithms 1-2).
  *   F         symmetric input in upper BSR (device)
  *   n_occ     number of occupied orbitals, 0 < n_occ < n
@@ -194,10 +231,15 @@ int sp2_density(sp2_ctx *ctx, const sp2_bsr *F, int64_t n_occ, double lmin, doub
 
 /* Vector-Jacobian product of the recorded (frozen schedule and masks) map
  * F -> D: Fbar = (dL/dF) for L = tr(W D), W symmetric in upper BSR on any
- * pattern.  X~_i are recomputed from the tape's checkpoints. */
+ * pattern.  X~_i are recomputed from the tape's checkpoints.  Each step
+ * Xbar <- cb G + cc (X~ G + G X~) runs in the arithmetic the forward used for
+ * that X~_i: FP64, or FP32 values with FP32 / BF16x3 products for the
+ * low-precision iterations of a mixed run.  The map excludes the subspace
+ * correction (sp2_options.correct). */
 int sp2_vjp(sp2_ctx *ctx, const sp2_tape *tape, const sp2_bsr *W, sp2_bsr **Fbar_out);
 
-/* Jacobian-vector product dD = (dD/dF) dF of the recorded map. */
+/* Jacobian-vector product dD = (dD/dF) dF of the recorded map (arithmetic
+ * per step as in sp2_vjp). */
 int sp2_jvp(sp2_ctx *ctx, const sp2_tape *tape, const sp2_bsr *dF, sp2_bsr **dD_out);
 
 /* The recorded map applied to another F (same n): schedule, n and masks
@@ -241,6 +283,23 @@ int sp2_homo_lumo(int bounds_mode, int n, const double *e, const double *trace, 
  * to FP32 first and return Xn rounded to FP32 values). */
 int sp2_square_step(sp2_ctx *ctx, const sp2_bsr *X, double a, double b, double c, int precision,
                     sp2_bsr **Xn_out, double sums[4]);
+
+/* Pair product of upper-BSR operands:
+ *   out = a I + b G + c (X Y + sign * Y X),  sign = +1 or -1,
+ * on the block pattern of X Y + Y X (upper blocks; the a I term touches only
+ * the n real diagonal entries).  sign = +1 is the anticommutator, the
+ * derivative of the square X^2 along Y that the adjoint recursion of
+ * Algorithm 2 applies (symmetric result); sign = -1 is the commutator
+ * (antisymmetric result for symmetric X and Y, or symmetric for an
+ * antisymmetric Y), as used by the subspace correction.  X is symmetric; Y is
+ * symmetric, or antisymmetric when y_antisym = 1 (a block below the diagonal
+ * is minus the transpose of its stored mirror, diagonal blocks are stored in
+ * full); G (symmetric, may be NULL) enters only at the output blocks it
+ * stores.  An antisymmetric result is returned as its upper blocks in the
+ * same format.  precision as in sp2_square_step.  sums[0] = ||out||_F^2 of the
+ * whole matrix, sums[1] = algorithmic flops (2 * 64^3 per block product). */
+int sp2_pair_product(sp2_ctx *ctx, const sp2_bsr *X, const sp2_bsr *Y, const sp2_bsr *G, int sign, int y_antisym,
+                     double a, double b, double c, int precision, sp2_bsr **out, double sums[2]);
 
 /* Truncation X~ = X + E with ||E|| <= tau in the chosen norm (section "Error
  * control"); diagonal blocks are never removed.  err[0] = ||E||_F,

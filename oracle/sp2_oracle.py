@@ -15,7 +15,9 @@ the density matrix with error control on distributed computer systems"
 * the truncation threshold schedule, eq. (tau_trunc), and the error-control
   bound on the occupied subspace (section "Error control");
 * the Frobenius and Frob-Inf truncation norms (section "Upper bounds for the
-  spectral norm").
+  spectral norm");
+* beyond the paper, for low-precision expansions: the first-order correction
+  of the occupied subspace, ``subspace_correction``.
 
 Matrices are stored dense in float64, with a symmetric boolean block mask
 (nbr x nbr, block size ``bs``) that records which blocks are structurally
@@ -726,6 +728,72 @@ def daleckii_krein_gradient(F, n_occ, W):
     C = (Yo.T @ W @ Yv) / (lam[:n_occ, None] - lam[None, n_occ:])
     G = Yo @ C @ Yv.T
     return G + G.T
+
+
+# ==========================================================================
+# occupied-subspace correction (extension for low-precision expansions)
+# ==========================================================================
+
+def _drop_small_blocks(X, beta, bs):
+    """Frobenius truncation of X with budget beta over its present blocks
+    (``truncate`` with the Frobenius norm); X may be antisymmetric."""
+    if beta <= 0.0:
+        return X
+    M = structural_mask(X, bs)
+    Xt, _, _ = truncate(X, M, beta, TRUNC_FROB, bs)
+    return Xt
+
+
+def subspace_correction(F, D, X_seq, p, alpha, lmin, lmax, *, rounds=1, purify=2, beta=0.0, tau_purify=0.0,
+                        trunc_norm=TRUNC_FROBINF, coarse_bs=4096, bs=BS):
+    """First-order correction of the occupied subspace of a near-projector D,
+    for expansions whose squares ran in low precision: the paper notes (section
+    "Error control") that an error in the occupied subspace made by one
+    iteration is not removed by later ones, so finishing in FP64 restores
+    idempotency and trace but keeps the subspace error.
+
+    With D = theta + E, E occupied-virtual, Delta = [D, [D, F]] =
+    D F (I - D) + (I - D) F D has occupied-virtual part (lambda_v - lambda_o)
+    E_ov in the eigenbasis of F; the derivative J of the map F -> theta(mu I - F)
+    divides that part by (lambda_o - lambda_v) (first-order perturbation of a
+    spectral projector), so D + J Delta = theta + O(||E||^2).  J is applied as
+    the derivative of the run's own polynomial steps along its iterates
+    X_seq = [X~_0, ..., X~_{n-1}] with polynomials p[1..n], alpha[1..n]:
+        dX~_0 = -Delta / (lmax - lmin),
+        p = 1: dX_i = a (Y dX~ + dX~ Y), Y = (1 - a) I + a X~_{i-1},
+        p = 0: dX_i = 2 a dX~ - a^2 (X~_{i-1} dX~ + dX~ X~_{i-1}),
+    without the run's masks.  C = [D, F], Delta and every dX_i lose their
+    smallest blocks within the Frobenius budget ``beta`` (0 = keep all).  Then
+    ``purify`` FP64 steps X^2, 2X - X^2, ... (each truncated with tau_purify in
+    ``trunc_norm``) restore idempotency.  Returns (D, info) with the norms of
+    Delta and of the correction of the last round."""
+    F = np.asarray(F, dtype=np.float64)
+    D = np.asarray(D, dtype=np.float64)
+    w = lmax - lmin
+    n = len(X_seq)
+    info = {}
+    for _ in range(rounds):
+        C = _drop_small_blocks(D @ F - F @ D, beta, bs)
+        Delta = D @ C - C @ D
+        dX = _drop_small_blocks(-Delta / w, beta, bs)
+        for i in range(n):
+            a = alpha[i + 1]
+            Xt = X_seq[i]
+            if p[i + 1] == 1:
+                Y = (1.0 - a) * np.eye(D.shape[0]) + a * Xt
+                dX = a * (Y @ dX + dX @ Y)
+            else:
+                dX = 2.0 * a * dX - a * a * (Xt @ dX + dX @ Xt)
+            dX = _drop_small_blocks(dX, beta, bs)
+        info = {"delta_norm": frobenius_norm(Delta), "step_norm": frobenius_norm(dX)}
+        P = D + dX
+        M = structural_mask(P, bs)
+        M[np.arange(M.shape[0]), np.arange(M.shape[0])] = True
+        for k in range(purify):
+            X = P @ P if k % 2 == 0 else 2.0 * P - P @ P
+            P, M, _ = truncate(X, pattern_square(M), tau_purify, trunc_norm, bs, coarse_bs)
+        D = P
+    return D, info
 
 
 # ==========================================================================

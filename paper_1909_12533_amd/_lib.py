@@ -25,7 +25,7 @@ EXPORTS = [
     "sp2_version", "sp2_options_default", "sp2_create", "sp2_destroy", "sp2_set_allocator", "sp2_trim",
     "sp2_last_error", "sp2_gershgorin", "sp2_density", "sp2_vjp", "sp2_jvp", "sp2_replay", "sp2_tape_info",
     "sp2_square_step", "sp2_truncate", "sp2_bsr_copy", "sp2_bsr_free", "sp2_tape_free", "sp2_schedule",
-    "sp2_homo_lumo",
+    "sp2_homo_lumo", "sp2_pair_product",
 ]
 
 
@@ -55,6 +55,9 @@ class sp2_options(C.Structure):
         ("idem_stop", C.c_double),
         ("record_tape", C.c_int32),
         ("n_checkpoints", C.c_int32),
+        ("correct", C.c_int32),
+        ("corr_purify", C.c_int32),
+        ("corr_tol", C.c_double),
     ]
 
 
@@ -91,6 +94,14 @@ class sp2_stats(C.Structure):
         ("nnzb", _LP),
         ("square_time_s", _DP),
         ("square_time_total_s", C.c_double),
+        ("corr_rounds", C.c_int32),
+        ("corr_time_s", C.c_double),
+        ("corr_flops", C.c_double),
+        ("corr_delta_norm", C.c_double),
+        ("corr_step_norm", C.c_double),
+        ("corr_e_last", C.c_double),
+        ("corr_max_nnzb", C.c_int64),
+        ("seq_bytes", C.c_int64),
     ]
 
 
@@ -139,6 +150,9 @@ def load(path: str = LIB_PATH):
     lib.sp2_square_step.restype = C.c_int
     lib.sp2_square_step.argtypes = [C.c_void_p, P(sp2_bsr), C.c_double, C.c_double, C.c_double, C.c_int,
                                     P(P(sp2_bsr)), P(C.c_double)]
+    lib.sp2_pair_product.restype = C.c_int
+    lib.sp2_pair_product.argtypes = [C.c_void_p, P(sp2_bsr), P(sp2_bsr), P(sp2_bsr), C.c_int, C.c_int, C.c_double,
+                                     C.c_double, C.c_double, C.c_int, P(P(sp2_bsr)), P(C.c_double)]
     lib.sp2_truncate.restype = C.c_int
     lib.sp2_truncate.argtypes = [C.c_void_p, P(sp2_bsr), C.c_double, C.c_int, C.c_int64, P(P(sp2_bsr)),
                                  P(C.c_double)]

@@ -140,8 +140,22 @@ void launch_build_maps(Ctx &c, const int32_t *row_of, const int32_t *col_idx, co
 void launch_popcount_rows(Ctx &c, const uint32_t *bits, int nbr, int W, int64_t *counts);
 void launch_extract_rows(Ctx &c, const uint32_t *bits, int nbr, int W, const int64_t *ptr, int32_t *cols,
                          int32_t *rows);
+// outbits row I (J >= I only) = OR of bits[K] over K in adj row I; with a
+// second (bits2, adj2) set also OR of bits2[K] over K in adj2 row I
 void launch_symbolic(Ctx &c, const uint32_t *bits, const int64_t *adj_ptr, const int32_t *adj_col, int nbr, int W,
-                     uint32_t *outbits);
+                     uint32_t *outbits, const uint32_t *bits2 = nullptr, const int64_t *adj_ptr2 = nullptr,
+                     const int32_t *adj_col2 = nullptr);
+// out = upper part (J >= I) of a | b (symmetric block-row bitmaps)
+void launch_or_upper(Ctx &c, const uint32_t *a, const uint32_t *b, int nbr, int W, uint32_t *out);
+// out (FP64, by output position) = a A + b B over an output pattern given by (row_of, col)
+void launch_add_union(Ctx &c, const int32_t *row_of, const int32_t *col, int64_t nblocks, int nbr, const void *pa,
+                      int preca, const int32_t *ia, double a, const void *pb, int precb, const int32_t *ib, double b,
+                      double *out);
+// diagonal blocks (B + sign B^T) / 2 in place (sign = 1 symmetric, -1 antisymmetric)
+void launch_sym_diag(Ctx &c, void *pool, int prec, const int64_t *row_ptr, const int32_t *col_idx,
+                     const int32_t *slot, int nbr, double sign);
+// nrm2[b] *= 2 for off-diagonal blocks (whole-matrix Frobenius weights)
+void launch_weight_offdiag(Ctx &c, double *nrm2, const int32_t *row_of, const int32_t *col, int64_t nblocks);
 // exclusive scan of n int64 counts into out[0..n] (out[n] = total)
 void scan_exclusive_i64(Ctx &c, const int64_t *in, int64_t *out, int64_t n);
 void launch_diag_missing(Ctx &c, const int64_t *row_ptr, const int32_t *col_idx, int nbr, int64_t *counts);
@@ -166,11 +180,26 @@ void launch_update(Ctx &c, const void *xpool, int xprec, const int32_t *xidxmap,
 constexpr int NPART = 5;  // per output block: e2 (weighted), trX, trS, ||out||^2, #K
 
 // tiled square: one workgroup per 2 x 2 tile of output blocks (kernels_tile.hip)
+// Tiled block product with symmetric (or antisymmetric) upper-stored operands
+// and an output on a given upper pattern:
+//   acc(I, J) = sum_K X_IK Y_KJ  [+ s2 * sum_K Y_IK X_KJ when npass == 2]
+//   out(I, J) = ca [I == J] I + cb G_IJ + cc acc(I, J)
+// The square of Algorithm 2 is X == Y, npass == 1, G == X.  A lower block of
+// an antisymmetric source (xanti / yanti) is minus the transpose of the stored
+// upper block.
 struct TileArgs {
   const void *xpool;
   int xprec;
-  const int32_t *idxmap;   // slot map of X
+  const int32_t *idxmap;   // slot map of X (symmetric: (I, J) and (J, I) give the stored block)
   const uint32_t *bits;    // block-row bitmaps of X
+  const void *ypool;       // second operand Y (same precision as X)
+  const int32_t *yidxmap;
+  const uint32_t *ybits;
+  int npass = 1;           // 1: X Y; 2: X Y + s2 Y X
+  int neg2 = 0;            // s2 = -1
+  int xanti = 0, yanti = 0;
+  const void *gpool;       // G of the cb term (same precision as X), or null
+  const int32_t *gidxmap;
   int nbr, W;
   const int32_t *oidx;     // nbr x nbr: pattern position of output block (I, J), or -1
   const int32_t *tiles;    // ntiles pairs (TI, TJ), TI <= TJ in units of 2 blocks
@@ -185,22 +214,6 @@ struct TileArgs {
 int64_t build_tiles(Ctx &c, const int32_t *oidx, int nbr, Buf &tiles);
 void launch_square_tile(Ctx &c, int mode, const TileArgs &a);
 void launch_square_tile_bf16x3(Ctx &c, const TileArgs &a);  // kernels_bf16x3.hip
-
-// anticommutator products for the adjoint (kernels_square.hip)
-struct AntiArgs {
-  const double *gpool;      // G values (FP64)
-  const int32_t *gidxmap;
-  const uint32_t *gbits;
-  const double *xpool;      // X values (FP64)
-  const int32_t *xidxmap;
-  const uint32_t *xbits;
-  int nbr, W;
-  const int32_t *out_row, *out_col;
-  int64_t nout;
-  double *opool;            // out = cb * G + cc * (G X + X G), slot = work index
-  double cb, cc;
-};
-void launch_anticommutator(Ctx &c, const AntiArgs &a);
 
 // truncation (kernels_trunc.hip)
 struct TruncOut {

@@ -51,7 +51,7 @@ __device__ inline f4 mfma_bf16(u32x4 a, u32x4 b, f4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, a), __builtin_bit_cast(bf8, b), c, 0, 0, 0);
 }
 
-template <typename TO>
+template <typename TO, bool GEN>
 __global__ __launch_bounds__(TPB, 1) void k_square_tile_bf16x3(TileArgs a) {
   // operand o (A0, A1, B0, B1) x plane (hi, lo)
   __shared__ __align__(16) uint16_t L[4][2][PLANE];
@@ -67,6 +67,7 @@ __global__ __launch_bounds__(TPB, 1) void k_square_tile_bf16x3(TileArgs a) {
   int32_t pos = -1;
   if (I < nbr && J < nbr && I <= J) pos = __builtin_amdgcn_readfirstlane(a.oidx[(int64_t)I * nbr + J]);
   const float *xp = static_cast<const float *>(a.xpool);
+  const float *yp = static_cast<const float *>(GEN ? a.ypool : a.xpool);
 
   f4 acc[4][4];
 #pragma unroll
@@ -74,18 +75,30 @@ __global__ __launch_bounds__(TPB, 1) void k_square_tile_bf16x3(TileArgs a) {
 #pragma unroll
     for (int n = 0; n < 4; ++n) acc[m][n] = f4{0, 0, 0, 0};
 
+  // K scan as in the FP64 / FP32 kernel (second pass: operands swapped)
+  const uint32_t *ybits = GEN ? a.ybits : a.bits;
   const uint32_t *bI0 = a.bits + (int64_t)I0 * W, *bI1 = a.bits + (int64_t)(has_i1 ? I0 + 1 : I0) * W;
-  const uint32_t *bJ0 = a.bits + (int64_t)J0 * W, *bJ1 = a.bits + (int64_t)(has_j1 ? J0 + 1 : J0) * W;
-  int wi = -1;
+  const uint32_t *bJ0 = ybits + (int64_t)J0 * W, *bJ1 = ybits + (int64_t)(has_j1 ? J0 + 1 : J0) * W;
+  int wi = -1, pass = 0, kpass = 0;
   uint32_t mask = 0u;
   auto next_k = [&]() -> int {
     while (mask == 0u) {
       ++wi;
-      if (wi >= W) return -1;
+      if (wi >= W) {
+        if (!GEN || pass + 1 >= a.npass) return -1;
+        ++pass;
+        wi = -1;
+        bI0 = a.ybits + (int64_t)I0 * W;
+        bI1 = a.ybits + (int64_t)(has_i1 ? I0 + 1 : I0) * W;
+        bJ0 = a.bits + (int64_t)J0 * W;
+        bJ1 = a.bits + (int64_t)(has_j1 ? J0 + 1 : J0) * W;
+        continue;
+      }
       const uint32_t ra = bI0[wi] | (has_i1 ? bI1[wi] : 0u);
       const uint32_t rb = bJ0[wi] | (has_j1 ? bJ1[wi] : 0u);
       mask = (uint32_t)__builtin_amdgcn_readfirstlane((int)(ra & rb));
     }
+    kpass = pass;
     const int K = wi * 32 + __builtin_ctz(mask);
     mask &= mask - 1u;
     return K;
@@ -95,12 +108,15 @@ __global__ __launch_bounds__(TPB, 1) void k_square_tile_bf16x3(TileArgs a) {
   u32x4 r0[4], r1[4], r2[4], r3[4];
   int32_t s0 = -1, s1 = -1, s2 = -1, s3 = -1;
   bool k0 = true, k1 = true, k2 = true, k3 = true;  // k runs along the stored columns
+  const float *p0 = xp, *p1 = xp, *p2 = yp, *p3 = yp;  // source pools of the staged blocks
+  uint32_t g0 = 0u, g1 = 0u, g2 = 0u, g3 = 0u;         // sign bit to flip per staged block
+  constexpr uint32_t SGN = 0x80000000u;
   const int cc = tid & 63, rg = tid >> 6;
 // row chunks (k along stored columns): 16-byte loads; column chunks: rows 16 rg + 4 jj + j of column cc
-#define SP2_LOAD(R, SL, KCOL)                                                                      \
+#define SP2_LOAD(R, P, SL, KCOL)                                                                   \
   do {                                                                                             \
     if ((SL) >= 0) {                                                                               \
-      const float *blk_ = xp + (int64_t)(SL) * BB;                                                 \
+      const float *blk_ = (P) + (int64_t)(SL) * BB;                                                \
       if (KCOL) {                                                                                  \
         const u32x4 *p_ = reinterpret_cast<const u32x4 *>(blk_) + tid;                             \
         _Pragma("unroll") for (int j = 0; j < 4; ++j) R[j] = p_[j * TPB];                          \
@@ -113,29 +129,41 @@ __global__ __launch_bounds__(TPB, 1) void k_square_tile_bf16x3(TileArgs a) {
       }                                                                                            \
     }                                                                                              \
   } while (0)
-#define SP2_ISSUE(KK)                                                                            \
-  do {                                                                                           \
-    s0 = __builtin_amdgcn_readfirstlane(a.idxmap[(int64_t)I0 * nbr + (KK)]);                     \
-    s1 = has_i1 ? __builtin_amdgcn_readfirstlane(a.idxmap[(int64_t)(I0 + 1) * nbr + (KK)]) : -1; \
-    s2 = __builtin_amdgcn_readfirstlane(a.idxmap[(int64_t)(KK) * nbr + J0]);                     \
-    s3 = has_j1 ? __builtin_amdgcn_readfirstlane(a.idxmap[(int64_t)(KK) * nbr + J0 + 1]) : -1;   \
-    k0 = I0 <= (KK);                                                                             \
-    k1 = I0 + 1 <= (KK);                                                                         \
-    k2 = (KK) > J0;                                                                              \
-    k3 = (KK) > J0 + 1;                                                                          \
-    SP2_LOAD(r0, s0, k0);                                                                        \
-    SP2_LOAD(r1, s1, k1);                                                                        \
-    SP2_LOAD(r2, s2, k2);                                                                        \
-    SP2_LOAD(r3, s3, k3);                                                                        \
+#define SP2_ISSUE(KK, KP)                                                                  \
+  do {                                                                                     \
+    const int32_t *li_ = (GEN && (KP)) ? a.yidxmap : a.idxmap;                             \
+    const int32_t *ri_ = GEN ? ((KP) ? a.idxmap : a.yidxmap) : a.idxmap;                   \
+    p0 = p1 = (GEN && (KP)) ? yp : xp;                                                     \
+    p2 = p3 = (GEN && (KP)) ? xp : yp;                                                     \
+    s0 = __builtin_amdgcn_readfirstlane(li_[(int64_t)I0 * nbr + (KK)]);                    \
+    s1 = has_i1 ? __builtin_amdgcn_readfirstlane(li_[(int64_t)(I0 + 1) * nbr + (KK)]) : -1; \
+    s2 = __builtin_amdgcn_readfirstlane(ri_[(int64_t)(KK) * nbr + J0]);                    \
+    s3 = has_j1 ? __builtin_amdgcn_readfirstlane(ri_[(int64_t)(KK) * nbr + J0 + 1]) : -1;  \
+    k0 = I0 <= (KK);                                                                       \
+    k1 = I0 + 1 <= (KK);                                                                   \
+    k2 = (KK) > J0;                                                                        \
+    k3 = (KK) > J0 + 1;                                                                    \
+    if (GEN) {                                                                             \
+      const bool la_ = (KP) ? a.yanti : a.xanti, ra_ = (KP) ? a.xanti : a.yanti;           \
+      const bool ng_ = (KP) && a.neg2;                                                     \
+      g0 = ((la_ && !k0) != ng_) ? SGN : 0u;                                               \
+      g1 = ((la_ && !k1) != ng_) ? SGN : 0u;                                               \
+      g2 = (ra_ && k2) ? SGN : 0u;                                                         \
+      g3 = (ra_ && k3) ? SGN : 0u;                                                         \
+    }                                                                                      \
+    SP2_LOAD(r0, p0, s0, k0);                                                              \
+    SP2_LOAD(r1, p1, s1, k1);                                                              \
+    SP2_LOAD(r2, p2, s2, k2);                                                              \
+    SP2_LOAD(r3, p3, s3, k3);                                                              \
   } while (0)
 // split and write one operand into its two planes, k-contiguous
-#define SP2_STORE(R, SL, KCOL, O)                                                                 \
+#define SP2_STORE(R, SL, KCOL, O, G)                                                              \
   do {                                                                                            \
     if ((SL) >= 0) {                                                                              \
       uint16_t *ph_ = L[O][0], *pl_ = L[O][1];                                                    \
       _Pragma("unroll") for (int j = 0; j < 4; ++j) {                                             \
         u32x2 hi_, lo_;                                                                           \
-        split4(R[j], hi_, lo_);                                                                   \
+        split4(GEN ? (R[j] ^ u32x4{(G), (G), (G), (G)}) : R[j], hi_, lo_);                        \
         int off_;                                                                                 \
         if (KCOL) {                                                                               \
           const int e_ = (j * TPB + tid) * 4;                                                     \
@@ -152,17 +180,17 @@ __global__ __launch_bounds__(TPB, 1) void k_square_tile_bf16x3(TileArgs a) {
   const int l16 = lane & 15, g = lane >> 4;
   int nk = 0;
   int K = next_k();
-  if (K >= 0) SP2_ISSUE(K);
+  if (K >= 0) SP2_ISSUE(K, kpass);
   while (K >= 0) {
     const int32_t c0 = s0, c1 = s1, c2 = s2, c3 = s3;
     __syncthreads();  // previous planes fully consumed
-    SP2_STORE(r0, c0, k0, 0);
-    SP2_STORE(r1, c1, k1, 1);
-    SP2_STORE(r2, c2, k2, 2);
-    SP2_STORE(r3, c3, k3, 3);
+    SP2_STORE(r0, c0, k0, 0, g0);
+    SP2_STORE(r1, c1, k1, 1, g1);
+    SP2_STORE(r2, c2, k2, 2, g2);
+    SP2_STORE(r3, c3, k3, 3, g3);
     __syncthreads();
     const int Kn = next_k();
-    if (Kn >= 0) SP2_ISSUE(Kn);  // next K's blocks in flight during the MFMAs
+    if (Kn >= 0) SP2_ISSUE(Kn, kpass);  // next K's blocks in flight during the MFMAs
     const int32_t sa = ia ? c1 : c0, sb = jb ? c3 : c2;
     if (pos >= 0 && sa >= 0 && sb >= 0) {
       const uint16_t *ah = L[ia][0], *al = L[ia][1], *bh = L[2 + jb][0], *bl = L[2 + jb][1];
@@ -200,7 +228,7 @@ __global__ __launch_bounds__(TPB, 1) void k_square_tile_bf16x3(TileArgs a) {
 #undef SP2_STORE
   if (pos < 0) return;
   // f32 16 x 16 accumulator layout: element v of lane group g is row 4 g + v
-  square_epilogue<float, TO>(acc, a, I, J, pos, xp, nk, [](int gg, int q) { return 4 * gg + q; });
+  square_epilogue<float, TO>(acc, a, I, J, pos, nk, [](int gg, int q) { return 4 * gg + q; });
 }
 
 }  // namespace
@@ -208,11 +236,19 @@ __global__ __launch_bounds__(TPB, 1) void k_square_tile_bf16x3(TileArgs a) {
 void launch_square_tile_bf16x3(Ctx &c, const TileArgs &a) {
   if (a.ntiles <= 0) return;
   if (a.xprec != P32) fail(SP2_ERR_INVALID_ARG, "BF16x3 square needs an FP32 input pool");
+  const bool gen = a.ypool != a.xpool || a.npass != 1 || a.xanti || a.yanti;
   const unsigned g = (unsigned)(8 * a.xcd_chunk);
-  if (a.oprec == P32)
-    k_square_tile_bf16x3<float><<<g, TPB, 0, c.stream>>>(a);
-  else
-    k_square_tile_bf16x3<double><<<g, TPB, 0, c.stream>>>(a);
+  if (a.oprec == P32) {
+    if (gen)
+      k_square_tile_bf16x3<float, true><<<g, TPB, 0, c.stream>>>(a);
+    else
+      k_square_tile_bf16x3<float, false><<<g, TPB, 0, c.stream>>>(a);
+  } else {
+    if (gen)
+      k_square_tile_bf16x3<double, true><<<g, TPB, 0, c.stream>>>(a);
+    else
+      k_square_tile_bf16x3<double, false><<<g, TPB, 0, c.stream>>>(a);
+  }
   SP2_LAUNCH_CHECK();
 }
 

@@ -123,7 +123,8 @@ __global__ void k_extract_rows(const uint32_t *bits, int nbr, int W, const int64
 
 // outbits[I] = OR over K in adj(I) of bits[K], restricted to columns J >= I.
 __global__ void k_symbolic(const uint32_t *bits, const int64_t *adj_ptr, const int32_t *adj_col, int nbr, int W,
-                           int WP, uint32_t *outbits) {
+                           int WP, uint32_t *outbits, const uint32_t *bits2, const int64_t *adj_ptr2,
+                           const int32_t *adj_col2) {
   __shared__ uint32_t sh[TPB];
   const int I = blockIdx.x;
   if (I >= nbr) return;
@@ -133,8 +134,11 @@ __global__ void k_symbolic(const uint32_t *bits, const int64_t *adj_ptr, const i
   for (int wb = 0; wb < W; wb += WP) {
     const int w = wb + wl;
     uint32_t acc = 0;
-    if (w < W)
+    if (w < W) {
       for (int64_t k = k0 + g; k < k1; k += G) acc |= bits[(int64_t)adj_col[k] * W + w];
+      if (bits2)
+        for (int64_t k = adj_ptr2[I] + g; k < adj_ptr2[I + 1]; k += G) acc |= bits2[(int64_t)adj_col2[k] * W + w];
+    }
     sh[threadIdx.x] = acc;
     __syncthreads();
     if (g == 0 && w < W) {
@@ -148,6 +152,20 @@ __global__ void k_symbolic(const uint32_t *bits, const int64_t *adj_ptr, const i
     }
     __syncthreads();
   }
+}
+
+// upper part (J >= I) of the union of two symmetric block-row bitmaps
+__global__ void k_or_upper(const uint32_t *a, const uint32_t *b, int nbr, int W, uint32_t *out) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= (int64_t)nbr * W) return;
+  const int I = (int)(i / W), w = (int)(i % W);
+  uint32_t v = a[i] | b[i];
+  const int lo = w * 32;
+  if (lo + 32 <= I)
+    v = 0u;
+  else if (lo < I)
+    v &= ~((1u << (I - lo)) - 1u);
+  out[i] = v;
 }
 
 // ---- 3-phase exclusive scan --------------------------------------------------
@@ -298,11 +316,19 @@ void launch_extract_rows(Ctx &c, const uint32_t *bits, int nbr, int W, const int
   SP2_LAUNCH_CHECK();
 }
 void launch_symbolic(Ctx &c, const uint32_t *bits, const int64_t *adj_ptr, const int32_t *adj_col, int nbr, int W,
-                     uint32_t *outbits) {
+                     uint32_t *outbits, const uint32_t *bits2, const int64_t *adj_ptr2, const int32_t *adj_col2) {
   if (nbr <= 0) return;
+  if (bits2 && !(adj_ptr2 && adj_col2)) fail(SP2_ERR_INVALID_ARG, "symbolic product: incomplete second operand");
   int WP = 1;
   while (WP < W && WP < TPB) WP <<= 1;
-  k_symbolic<<<nbr, TPB, 0, c.stream>>>(bits, adj_ptr, adj_col, nbr, W, WP, outbits);
+  k_symbolic<<<nbr, TPB, 0, c.stream>>>(bits, adj_ptr, adj_col, nbr, W, WP, outbits, bits2, adj_ptr2, adj_col2);
+  SP2_LAUNCH_CHECK();
+}
+
+void launch_or_upper(Ctx &c, const uint32_t *a, const uint32_t *b, int nbr, int W, uint32_t *out) {
+  const int64_t n = (int64_t)nbr * W;
+  if (n <= 0) return;
+  k_or_upper<<<(unsigned)((n + TPB - 1) / TPB), TPB, 0, c.stream>>>(a, b, nbr, W, out);
   SP2_LAUNCH_CHECK();
 }
 

@@ -87,7 +87,10 @@ __device__ inline void mma_dispatch(typename MF<T>::acc_t (&acc)[4][4], const T 
 }
 
 
-template <typename T, typename TO>
+// GEN: general product (second operand Y, optional second pass with the
+// roles swapped, sign flips of antisymmetric lower blocks); otherwise the
+// square X X with the same code minus that bookkeeping.
+template <typename T, typename TO, bool GEN>
 __global__ __launch_bounds__(TPB, 1) void k_square_tile(TileArgs a) {
   constexpr int LD = MF<T>::LD;
   __shared__ __align__(16) T As[2][64 * LD];
@@ -97,13 +100,12 @@ __global__ __launch_bounds__(TPB, 1) void k_square_tile(TileArgs a) {
   const int nbr = a.nbr, W = a.W;
   const int I0 = 2 * __builtin_amdgcn_readfirstlane(a.tiles[2 * t]);
   const int J0 = 2 * __builtin_amdgcn_readfirstlane(a.tiles[2 * t + 1]);
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wave = threadIdx.x >> 6;
   const int ia = wave >> 1, jb = wave & 1;
   const int I = I0 + ia, J = J0 + jb;
   const bool has_i1 = I0 + 1 < nbr, has_j1 = J0 + 1 < nbr;
   int32_t pos = -1;
   if (I < nbr && J < nbr && I <= J) pos = __builtin_amdgcn_readfirstlane(a.oidx[(int64_t)I * nbr + J]);
-  const T *xp = static_cast<const T *>(a.xpool);
 
   typename MF<T>::acc_t acc[4][4];
 #pragma unroll
@@ -111,70 +113,115 @@ __global__ __launch_bounds__(TPB, 1) void k_square_tile(TileArgs a) {
 #pragma unroll
     for (int n = 0; n < 4; ++n) acc[m][n] = typename MF<T>::acc_t{0, 0, 0, 0};
 
-  // K over the union of the four blocks' K sets
+  // K over the union of the four blocks' K sets (rows I0, I0+1 of the left
+  // operand, columns J0, J0+1 of the right one); with two passes the scan
+  // restarts with the operands swapped
+  const uint32_t *ybits = GEN ? a.ybits : a.bits;
   const uint32_t *bI0 = a.bits + (int64_t)I0 * W, *bI1 = a.bits + (int64_t)(has_i1 ? I0 + 1 : I0) * W;
-  const uint32_t *bJ0 = a.bits + (int64_t)J0 * W, *bJ1 = a.bits + (int64_t)(has_j1 ? J0 + 1 : J0) * W;
-  int wi = -1;
+  const uint32_t *bJ0 = ybits + (int64_t)J0 * W, *bJ1 = ybits + (int64_t)(has_j1 ? J0 + 1 : J0) * W;
+  int wi = -1, pass = 0, kpass = 0;
   uint32_t mask = 0u;
   auto next_k = [&]() -> int {
     while (mask == 0u) {
       ++wi;
-      if (wi >= W) return -1;
+      if (wi >= W) {
+        if (!GEN || pass + 1 >= a.npass) return -1;
+        ++pass;
+        wi = -1;
+        bI0 = a.ybits + (int64_t)I0 * W;
+        bI1 = a.ybits + (int64_t)(has_i1 ? I0 + 1 : I0) * W;
+        bJ0 = a.bits + (int64_t)J0 * W;
+        bJ1 = a.bits + (int64_t)(has_j1 ? J0 + 1 : J0) * W;
+        continue;
+      }
       const uint32_t ra = bI0[wi] | (has_i1 ? bI1[wi] : 0u);
       const uint32_t rb = bJ0[wi] | (has_j1 ? bJ1[wi] : 0u);
       mask = (uint32_t)__builtin_amdgcn_readfirstlane((int)(ra & rb));
     }
+    kpass = pass;
     const int K = wi * 32 + __builtin_ctz(mask);
     mask &= mask - 1u;
     return K;
   };
 
-  // staged operand blocks A0 = X_{I0,K}, A1 = X_{I0+1,K}, B0 = X_{K,J0}, B1 = X_{K,J0+1}
+  // staged operand blocks A0 = L_{I0,K}, A1 = L_{I0+1,K}, B0 = R_{K,J0}, B1 = R_{K,J0+1}
+  // with (L, R) = (X, Y) in the first pass and (Y, X) in the second
   constexpr int NCH = Stage<T>::NCH;
   constexpr int QB = BB * (int)sizeof(T) / 16;  // 16-byte chunks per block
-  const u32x4 *xq = reinterpret_cast<const u32x4 *>(xp);
+  constexpr uint32_t SGN = 0x80000000u;
+  const u32x4 *xq = reinterpret_cast<const u32x4 *>(a.xpool);
+  const u32x4 *yq = reinterpret_cast<const u32x4 *>(GEN ? a.ypool : a.xpool);
   u32x4 r0[NCH], r1[NCH], r2[NCH], r3[NCH];
   int32_t s0 = -1, s1 = -1, s2 = -1, s3 = -1;
+  uint32_t g0 = 0u, g1 = 0u, g2 = 0u, g3 = 0u;  // sign bit to flip per staged block
 // absent block (slot < 0): zeros, and no load is issued (wave-uniform branch)
-#define SP2_LOAD_BLOCK(R, SL)                                                     \
+#define SP2_LOAD_BLOCK(R, Q, SL)                                                  \
   do {                                                                            \
     if ((SL) >= 0) {                                                              \
-      const u32x4 *src_ = xq + (int64_t)(SL) * QB + threadIdx.x;                  \
+      const u32x4 *src_ = (Q) + (int64_t)(SL) * QB + threadIdx.x;                 \
       _Pragma("unroll") for (int j = 0; j < NCH; ++j) R[j] = src_[j * TPB];       \
     } else {                                                                      \
       _Pragma("unroll") for (int j = 0; j < NCH; ++j) R[j] = u32x4{0u, 0u, 0u, 0u}; \
     }                                                                             \
   } while (0)
-#define SP2_ISSUE(KK)                                                                                 \
-  do {                                                                                                \
-    s0 = __builtin_amdgcn_readfirstlane(a.idxmap[(int64_t)I0 * nbr + (KK)]);                          \
-    s1 = has_i1 ? __builtin_amdgcn_readfirstlane(a.idxmap[(int64_t)(I0 + 1) * nbr + (KK)]) : -1;      \
-    s2 = __builtin_amdgcn_readfirstlane(a.idxmap[(int64_t)(KK) * nbr + J0]);                          \
-    s3 = has_j1 ? __builtin_amdgcn_readfirstlane(a.idxmap[(int64_t)(KK) * nbr + J0 + 1]) : -1;        \
-    SP2_LOAD_BLOCK(r0, s0);                                                                           \
-    SP2_LOAD_BLOCK(r1, s1);                                                                           \
-    SP2_LOAD_BLOCK(r2, s2);                                                                           \
-    SP2_LOAD_BLOCK(r3, s3);                                                                           \
+#define SP2_ISSUE(KK, KP)                                                                                  \
+  do {                                                                                                     \
+    const int32_t *li_ = (GEN && (KP)) ? a.yidxmap : a.idxmap;                                             \
+    const int32_t *ri_ = GEN ? ((KP) ? a.idxmap : a.yidxmap) : a.idxmap;                                   \
+    const u32x4 *lq_ = (GEN && (KP)) ? yq : xq, *rq_ = (GEN && (KP)) ? xq : yq;                            \
+    s0 = __builtin_amdgcn_readfirstlane(li_[(int64_t)I0 * nbr + (KK)]);                                    \
+    s1 = has_i1 ? __builtin_amdgcn_readfirstlane(li_[(int64_t)(I0 + 1) * nbr + (KK)]) : -1;                \
+    s2 = __builtin_amdgcn_readfirstlane(ri_[(int64_t)(KK) * nbr + J0]);                                    \
+    s3 = has_j1 ? __builtin_amdgcn_readfirstlane(ri_[(int64_t)(KK) * nbr + J0 + 1]) : -1;                  \
+    if (GEN) {                                                                                             \
+      const bool la_ = (KP) ? a.yanti : a.xanti, ra_ = (KP) ? a.xanti : a.yanti;                           \
+      const bool ng_ = (KP) && a.neg2;                                                                     \
+      g0 = ((la_ && I0 > (KK)) != ng_) ? SGN : 0u;                                                         \
+      g1 = ((la_ && I0 + 1 > (KK)) != ng_) ? SGN : 0u;                                                     \
+      g2 = (ra_ && (KK) > J0) ? SGN : 0u;                                                                  \
+      g3 = (ra_ && (KK) > J0 + 1) ? SGN : 0u;                                                              \
+    }                                                                                                      \
+    SP2_LOAD_BLOCK(r0, lq_, s0);                                                                           \
+    SP2_LOAD_BLOCK(r1, lq_, s1);                                                                           \
+    SP2_LOAD_BLOCK(r2, rq_, s2);                                                                           \
+    SP2_LOAD_BLOCK(r3, rq_, s3);                                                                           \
   } while (0)
 
   int nk = 0;
   int K = next_k();
-  if (K >= 0) SP2_ISSUE(K);
+  if (K >= 0) SP2_ISSUE(K, kpass);
   while (K >= 0) {
     const int32_t c0 = s0, c1 = s1, c2 = s2, c3 = s3;
     __syncthreads();  // previous tiles fully consumed
+    if (GEN) {
+      // sign flips on the staged words (FP64: the high word of each double)
+      const uint32_t lo0 = sizeof(T) == 8 ? 0u : g0, lo1 = sizeof(T) == 8 ? 0u : g1;
+      const uint32_t lo2 = sizeof(T) == 8 ? 0u : g2, lo3 = sizeof(T) == 8 ? 0u : g3;
+      const u32x4 m0 = u32x4{lo0, g0, lo0, g0}, m1 = u32x4{lo1, g1, lo1, g1};
+      const u32x4 m2 = u32x4{lo2, g2, lo2, g2}, m3 = u32x4{lo3, g3, lo3, g3};
 #pragma unroll
-    for (int j = 0; j < NCH; ++j) {
-      const int e = (j * TPB + (int)threadIdx.x) * Stage<T>::EPC;
-      const int o = (e >> 6) * LD + (e & 63);
-      *reinterpret_cast<u32x4 *>(&As[0][o]) = r0[j];
-      *reinterpret_cast<u32x4 *>(&As[1][o]) = r1[j];
-      *reinterpret_cast<u32x4 *>(&Bs[0][o]) = r2[j];
-      *reinterpret_cast<u32x4 *>(&Bs[1][o]) = r3[j];
+      for (int j = 0; j < NCH; ++j) {
+        const int e = (j * TPB + (int)threadIdx.x) * Stage<T>::EPC;
+        const int o = (e >> 6) * LD + (e & 63);
+        *reinterpret_cast<u32x4 *>(&As[0][o]) = r0[j] ^ m0;
+        *reinterpret_cast<u32x4 *>(&As[1][o]) = r1[j] ^ m1;
+        *reinterpret_cast<u32x4 *>(&Bs[0][o]) = r2[j] ^ m2;
+        *reinterpret_cast<u32x4 *>(&Bs[1][o]) = r3[j] ^ m3;
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < NCH; ++j) {
+        const int e = (j * TPB + (int)threadIdx.x) * Stage<T>::EPC;
+        const int o = (e >> 6) * LD + (e & 63);
+        *reinterpret_cast<u32x4 *>(&As[0][o]) = r0[j];
+        *reinterpret_cast<u32x4 *>(&As[1][o]) = r1[j];
+        *reinterpret_cast<u32x4 *>(&Bs[0][o]) = r2[j];
+        *reinterpret_cast<u32x4 *>(&Bs[1][o]) = r3[j];
+      }
     }
     __syncthreads();
     const int Kn = next_k();
-    if (Kn >= 0) SP2_ISSUE(Kn);  // next K's blocks in flight during the MFMAs
+    if (Kn >= 0) SP2_ISSUE(Kn, kpass);  // next K's blocks in flight during the MFMAs
     const int32_t sa = ia ? c1 : c0, sb = jb ? c3 : c2;
     if (pos >= 0 && sa >= 0 && sb >= 0) {
       mma_dispatch<T>(acc, ia ? As[1] : As[0], jb ? Bs[1] : Bs[0], I > K, K > J);
@@ -186,7 +233,7 @@ __global__ __launch_bounds__(TPB, 1) void k_square_tile(TileArgs a) {
 #undef SP2_LOAD_BLOCK
   if (pos < 0) return;
 
-  square_epilogue<T, TO>(acc, a, I, J, pos, xp, nk, [](int g, int q) { return MF<T>::row(g, q); });
+  square_epilogue<T, TO>(acc, a, I, J, pos, nk, [](int g, int q) { return MF<T>::row(g, q); });
 }
 
 // Tile order: super-tiles of ST x ST tiles (2 ST x 2 ST output blocks) in
@@ -253,16 +300,29 @@ int64_t build_tiles(Ctx &c, const int32_t *oidx, int nbr, Buf &tiles) {
 
 void launch_square_tile(Ctx &c, int mode, const TileArgs &a) {
   if (a.ntiles <= 0) return;
+  const bool gen = a.ypool != a.xpool || a.npass != 1 || a.xanti || a.yanti;
+  if (gen && !(a.ypool && a.yidxmap && a.ybits && (a.npass == 1 || a.npass == 2)))
+    fail(SP2_ERR_INVALID_ARG, "tiled product: incomplete second operand");
   const unsigned g = (unsigned)(8 * a.xcd_chunk);
   if (mode == M_F64) {
     if (a.xprec != P64 || a.oprec != P64) fail(SP2_ERR_INVALID_ARG, "FP64 square needs FP64 pools");
-    k_square_tile<double, double><<<g, TPB, 0, c.stream>>>(a);
+    if (gen)
+      k_square_tile<double, double, true><<<g, TPB, 0, c.stream>>>(a);
+    else
+      k_square_tile<double, double, false><<<g, TPB, 0, c.stream>>>(a);
   } else if (mode == M_F32) {
     if (a.xprec != P32) fail(SP2_ERR_INVALID_ARG, "FP32 square needs an FP32 input pool");
-    if (a.oprec == P32)
-      k_square_tile<float, float><<<g, TPB, 0, c.stream>>>(a);
-    else
-      k_square_tile<float, double><<<g, TPB, 0, c.stream>>>(a);
+    if (a.oprec == P32) {
+      if (gen)
+        k_square_tile<float, float, true><<<g, TPB, 0, c.stream>>>(a);
+      else
+        k_square_tile<float, float, false><<<g, TPB, 0, c.stream>>>(a);
+    } else {
+      if (gen)
+        k_square_tile<float, double, true><<<g, TPB, 0, c.stream>>>(a);
+      else
+        k_square_tile<float, double, false><<<g, TPB, 0, c.stream>>>(a);
+    }
   } else if (mode == M_BF16X3) {
     launch_square_tile_bf16x3(c, a);
     return;

@@ -99,6 +99,54 @@ __global__ void k_gather(const S *src, const int32_t *slot, int64_t nblocks, D *
   for (int e = threadIdx.x; e < BB; e += blockDim.x) out[e] = (D)in[e];
 }
 
+// out block b = a A_(I,J) + b B_(I,J) for the output block (I, J) = (row_of[b], col[b]);
+// an operand without the block contributes zero
+template <typename SA, typename SB>
+__global__ void k_add_union(const int32_t *row_of, const int32_t *col, int64_t nblocks, int nbr, const SA *pa,
+                            const int32_t *ia, double a, const SB *pb, const int32_t *ib, double b, double *out) {
+  const int64_t o = blockIdx.x;
+  if (o >= nblocks) return;
+  const int64_t k = (int64_t)row_of[o] * nbr + col[o];
+  const int32_t sa = ia[k], sb = ib[k];
+  double *ob = out + o * BB;
+  for (int e = threadIdx.x; e < BB; e += blockDim.x) {
+    double v = 0.0;
+    if (sa >= 0) v += a * (double)pa[(int64_t)sa * BB + e];
+    if (sb >= 0) v += b * (double)pb[(int64_t)sb * BB + e];
+    ob[e] = v;
+  }
+}
+
+// block norms^2 weighted for the whole symmetric matrix: x2 off the diagonal
+__global__ void k_weight_offdiag(double *nrm2, const int32_t *row_of, const int32_t *col, int64_t nblocks) {
+  const int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (b < nblocks && row_of[b] != col[b]) nrm2[b] *= 2.0;
+}
+
+// diagonal blocks made exactly symmetric, (B + B^T) / 2 (sign = 1), or
+// antisymmetric, (B - B^T) / 2 (sign = -1): a square computes the (r, c) and
+// (c, r) entries of a diagonal block separately, so they differ by rounding.
+// The diagonal block (I, I), when stored, is the first block of row I.
+template <typename T>
+__global__ void k_sym_diag(T *pool, const int64_t *row_ptr, const int32_t *col_idx, const int32_t *slot, int nbr,
+                           double sign) {
+  const int I = blockIdx.x;
+  if (I >= nbr) return;
+  const int64_t b = row_ptr[I];
+  if (b >= row_ptr[I + 1] || col_idx[b] != I) return;
+  T *blk = pool + (int64_t)(slot ? slot[b] : b) * BB;
+  for (int e = threadIdx.x; e < BB; e += blockDim.x) {
+    const int r = e >> 6, c = e & 63;
+    if (r < c) {
+      const double m = 0.5 * ((double)blk[r * 64 + c] + sign * (double)blk[c * 64 + r]);
+      blk[r * 64 + c] = (T)m;
+      blk[c * 64 + r] = (T)(sign * m);
+    } else if (r == c && sign < 0.0) {
+      blk[e] = (T)0;
+    }
+  }
+}
+
 // deterministic sum over rows of a [nrows][ncols] array (ncols <= 8)
 __device__ double block_sum(double v) {
   __shared__ double sh[TPB / 64];
@@ -206,6 +254,42 @@ void launch_gather(Ctx &c, const void *src, int src_prec, const int32_t *slot, i
     k_gather<float, double><<<g, TPB, 0, c.stream>>>((const float *)src, slot, nblocks, (double *)dst);
   else
     k_gather<float, float><<<g, TPB, 0, c.stream>>>((const float *)src, slot, nblocks, (float *)dst);
+  SP2_LAUNCH_CHECK();
+}
+
+void launch_add_union(Ctx &c, const int32_t *row_of, const int32_t *col, int64_t nblocks, int nbr, const void *pa,
+                      int preca, const int32_t *ia, double a, const void *pb, int precb, const int32_t *ib, double b,
+                      double *out) {
+  if (nblocks <= 0) return;
+  const unsigned g = (unsigned)nblocks;
+  if (preca == P64 && precb == P64)
+    k_add_union<double, double><<<g, TPB, 0, c.stream>>>(row_of, col, nblocks, nbr, (const double *)pa, ia, a,
+                                                         (const double *)pb, ib, b, out);
+  else if (preca == P64 && precb == P32)
+    k_add_union<double, float><<<g, TPB, 0, c.stream>>>(row_of, col, nblocks, nbr, (const double *)pa, ia, a,
+                                                        (const float *)pb, ib, b, out);
+  else if (preca == P32 && precb == P64)
+    k_add_union<float, double><<<g, TPB, 0, c.stream>>>(row_of, col, nblocks, nbr, (const float *)pa, ia, a,
+                                                        (const double *)pb, ib, b, out);
+  else
+    k_add_union<float, float><<<g, TPB, 0, c.stream>>>(row_of, col, nblocks, nbr, (const float *)pa, ia, a,
+                                                       (const float *)pb, ib, b, out);
+  SP2_LAUNCH_CHECK();
+}
+
+void launch_weight_offdiag(Ctx &c, double *nrm2, const int32_t *row_of, const int32_t *col, int64_t nblocks) {
+  if (nblocks <= 0) return;
+  k_weight_offdiag<<<(unsigned)((nblocks + TPB - 1) / TPB), TPB, 0, c.stream>>>(nrm2, row_of, col, nblocks);
+  SP2_LAUNCH_CHECK();
+}
+
+void launch_sym_diag(Ctx &c, void *pool, int prec, const int64_t *row_ptr, const int32_t *col_idx,
+                     const int32_t *slot, int nbr, double sign) {
+  if (nbr <= 0) return;
+  if (prec == P64)
+    k_sym_diag<double><<<(unsigned)nbr, TPB, 0, c.stream>>>((double *)pool, row_ptr, col_idx, slot, nbr, sign);
+  else
+    k_sym_diag<float><<<(unsigned)nbr, TPB, 0, c.stream>>>((float *)pool, row_ptr, col_idx, slot, nbr, sign);
   SP2_LAUNCH_CHECK();
 }
 

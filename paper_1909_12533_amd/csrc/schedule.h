@@ -123,13 +123,16 @@ inline void poly_coeffs(int p, double alpha, double &a, double &b, double &c) {
 // the forward bounds in bounds mode.  Returns {homo_ub, lumo_lb} (NaN if none).
 inline void homo_lumo(const Sched &s, const std::vector<double> &e, const std::vector<double> &tr,
                       const std::vector<int> &p, const std::vector<double> &alpha, int n, double lmin, double lmax,
-                      int64_t N, int64_t n_occ, double &homo, double &lumo) {
+                      int64_t N, int64_t n_occ, double &homo, double &lumo, const std::vector<double> *unit = nullptr) {
+  // e_i below 1e3 u sqrt(N) is rounding noise rather than an eigenvalue's
+  // distance from {0, 1}; u = 2^-52, or per iteration the unit roundoff of
+  // the arithmetic that produced e_i (unit[i])
   const double w = lmax - lmin;
-  const double e_floor = 1e3 * DELTA_N * std::sqrt((double)N);
   double bh = std::numeric_limits<double>::infinity();
   double bl = -std::numeric_limits<double>::infinity();
   for (int i = 0; i <= n; ++i) {
     const double ei = e[i];
+    const double e_floor = 1e3 * (unit ? (*unit)[i] : DELTA_N) * std::sqrt((double)N);
     if (!(ei >= e_floor && ei < 0.25)) continue;
     const double u = 2.0 * ei / (1.0 + std::sqrt(1.0 - 4.0 * ei));
     bool ok;

@@ -120,25 +120,39 @@ Maps build_maps(Ctx &c, const Pattern &p, bool with_adj) {
   return m;
 }
 
+// upper block pattern from block-row bitmaps (J >= I bits only), slot = position
+Pattern pattern_from_bits(Ctx &c, int64_t n, int nbr, int W, const Buf &outbits) {
+  Pattern o;
+  o.n = n;
+  o.nbr = nbr;
+  Buf cnt = c.alloc(sizeof(int64_t) * nbr);
+  launch_popcount_rows(c, outbits.as<uint32_t>(), nbr, W, cnt.as<int64_t>());
+  o.row_ptr = c.alloc(sizeof(int64_t) * (nbr + 1));
+  scan_exclusive_i64(c, cnt.as<int64_t>(), o.row_ptr.as<int64_t>(), nbr);
+  c.d2h(&o.nnzb, o.row_ptr.as<int64_t>() + nbr, sizeof(int64_t));
+  if (o.nnzb > (int64_t)0x7fffffff) fail(SP2_ERR_INVALID_ARG, "product pattern exceeds 2^31 blocks");
+  o.col_idx = c.alloc(sizeof(int32_t) * (o.nnzb > 0 ? o.nnzb : 1));
+  o.row_of = c.alloc(sizeof(int32_t) * (o.nnzb > 0 ? o.nnzb : 1));
+  launch_extract_rows(c, outbits.as<uint32_t>(), nbr, W, o.row_ptr.as<int64_t>(), o.col_idx.as<int32_t>(),
+                      o.row_of.as<int32_t>());
+  return o;  // slot empty: identity
+}
+
 // block pattern of X^2 (upper blocks), output slot = position
 Pattern symbolic_square(Ctx &c, const Pattern &p, const Maps &m) {
   Buf outbits = c.alloc(sizeof(uint32_t) * (size_t)p.nbr * m.W);
   launch_symbolic(c, m.bits.as<uint32_t>(), m.adj_ptr.as<int64_t>(), m.adj_col.as<int32_t>(), p.nbr, m.W,
                   outbits.as<uint32_t>());
-  Pattern o;
-  o.n = p.n;
-  o.nbr = p.nbr;
-  Buf cnt = c.alloc(sizeof(int64_t) * p.nbr);
-  launch_popcount_rows(c, outbits.as<uint32_t>(), p.nbr, m.W, cnt.as<int64_t>());
-  o.row_ptr = c.alloc(sizeof(int64_t) * (p.nbr + 1));
-  scan_exclusive_i64(c, cnt.as<int64_t>(), o.row_ptr.as<int64_t>(), p.nbr);
-  c.d2h(&o.nnzb, o.row_ptr.as<int64_t>() + p.nbr, sizeof(int64_t));
-  if (o.nnzb > (int64_t)0x7fffffff) fail(SP2_ERR_INVALID_ARG, "square pattern exceeds 2^31 blocks");
-  o.col_idx = c.alloc(sizeof(int32_t) * (o.nnzb > 0 ? o.nnzb : 1));
-  o.row_of = c.alloc(sizeof(int32_t) * (o.nnzb > 0 ? o.nnzb : 1));
-  launch_extract_rows(c, outbits.as<uint32_t>(), p.nbr, m.W, o.row_ptr.as<int64_t>(), o.col_idx.as<int32_t>(),
-                      o.row_of.as<int32_t>());
-  return o;  // slot empty: identity
+  return pattern_from_bits(c, p.n, p.nbr, m.W, outbits);
+}
+
+// block pattern of X Y + Y X (upper blocks) for symmetric patterns of X and Y
+Pattern symbolic_pair(Ctx &c, int64_t n, const Maps &mx, const Maps &my) {
+  Buf outbits = c.alloc(sizeof(uint32_t) * (size_t)mx.nbr * mx.W);
+  launch_symbolic(c, my.bits.as<uint32_t>(), mx.adj_ptr.as<int64_t>(), mx.adj_col.as<int32_t>(), mx.nbr, mx.W,
+                  outbits.as<uint32_t>(), mx.bits.as<uint32_t>(), my.adj_ptr.as<int64_t>(),
+                  my.adj_col.as<int32_t>());
+  return pattern_from_bits(c, n, mx.nbr, mx.W, outbits);
 }
 
 std::shared_ptr<Pool> new_pool(Ctx &c, int prec, int64_t nslots) {
@@ -253,6 +267,11 @@ SquareOut square_step(Ctx &c, const DMat &X, const Maps &m, int mode, int oprec,
   ta.xprec = X.pool->prec;
   ta.idxmap = m.idxmap.as<int32_t>();
   ta.bits = m.bits.as<uint32_t>();
+  ta.ypool = ta.xpool;
+  ta.yidxmap = ta.idxmap;
+  ta.ybits = ta.bits;
+  ta.gpool = ta.xpool;
+  ta.gidxmap = ta.idxmap;
   ta.nbr = X.pat.nbr;
   ta.W = m.W;
   ta.oidx = om.idxmap.as<int32_t>();
@@ -277,6 +296,92 @@ SquareOut square_step(Ctx &c, const DMat &X, const Maps &m, int mode, int oprec,
   SP2_HIP(hipEventElapsedTime(&ms, ev.a, ev.b));
   r.kernel_s = 1e-3 * (double)ms;
   return r;
+}
+
+// Options of a two-operand product (the tiled kernel's general mode)
+struct PairOpt {
+  bool neg2 = false;             // X Y - Y X instead of X Y + Y X
+  bool yanti = false;            // Y antisymmetric (upper blocks stored)
+  const DMat *G = nullptr;       // matrix of the cb term
+  const Maps *mg = nullptr;
+  double ca = 0.0, cb = 0.0, cc = 1.0;
+  int mode = M_F64, oprec = P64;
+  const Pattern *outpat = nullptr;  // output pattern; default the block pattern of X Y + Y X
+};
+
+// out = ca I + cb G + cc (X Y +- Y X) on upper blocks.  X, Y (and G) hold
+// values in the precision the mode multiplies (FP64 or FP32); the maps need
+// adjacency lists when the output pattern is the product's own.
+SquareOut pair_product(Ctx &c, const DMat &X, const Maps &mx, const DMat &Y, const Maps &my, const PairOpt &po) {
+  const int need = po.mode == M_F64 ? P64 : P32;
+  if (X.pool->prec != need || Y.pool->prec != need || (po.G && po.G->pool->prec != need))
+    fail(SP2_ERR_INVALID_ARG, "pair product: operand precision does not match the arithmetic");
+  if (X.pat.nbr != Y.pat.nbr) fail(SP2_ERR_INVALID_ARG, "pair product: operand sizes differ");
+  SquareOut r;
+  if (po.outpat) {
+    r.next.pat = clone_pattern(c, *po.outpat);
+    r.next.pat.slot.reset();
+  } else {
+    r.next.pat = symbolic_pair(c, X.pat.n, mx, my);
+  }
+  const int64_t nout = r.next.pat.nnzb;
+  r.next.pool = new_pool(c, po.oprec, nout);
+  r.parts = c.alloc(sizeof(double) * NPART * (size_t)(nout > 0 ? nout : 1));
+  Maps om = build_maps(c, r.next.pat, false);
+  Buf tiles;
+  const int64_t ntiles = build_tiles(c, om.idxmap.as<int32_t>(), X.pat.nbr, tiles);
+  TileArgs ta;
+  ta.xpool = X.pool->vals.p;
+  ta.xprec = X.pool->prec;
+  ta.idxmap = mx.idxmap.as<int32_t>();
+  ta.bits = mx.bits.as<uint32_t>();
+  ta.ypool = Y.pool->vals.p;
+  ta.yidxmap = my.idxmap.as<int32_t>();
+  ta.ybits = my.bits.as<uint32_t>();
+  ta.npass = 2;
+  ta.neg2 = po.neg2 ? 1 : 0;
+  ta.xanti = 0;
+  ta.yanti = po.yanti ? 1 : 0;
+  ta.gpool = po.G ? po.G->pool->vals.p : nullptr;
+  ta.gidxmap = po.G ? po.mg->idxmap.as<int32_t>() : nullptr;
+  ta.nbr = X.pat.nbr;
+  ta.W = mx.W;
+  ta.oidx = om.idxmap.as<int32_t>();
+  ta.tiles = tiles.as<int32_t>();
+  ta.ntiles = ntiles;
+  ta.xcd_chunk = (ntiles + 7) / 8;
+  ta.opool = r.next.pool->vals.p;
+  ta.oprec = po.oprec;
+  ta.ca = po.ca;
+  ta.cb = po.cb;
+  ta.cc = po.cc;
+  ta.n = X.pat.n;
+  ta.parts = r.parts.as<double>();
+  EventPair ev;
+  SP2_HIP(hipEventRecord(ev.a, c.stream));
+  launch_square_tile(c, po.mode, ta);
+  SP2_HIP(hipEventRecord(ev.b, c.stream));
+  Buf sums = c.alloc(sizeof(double) * NPART);
+  launch_reduce_parts(c, ta.parts, nout, NPART, sums.as<double>());
+  c.d2h(r.sums, sums.p, sizeof(double) * NPART);
+  float ms = 0.0f;
+  SP2_HIP(hipEventElapsedTime(&ms, ev.a, ev.b));
+  r.kernel_s = 1e-3 * (double)ms;
+  return r;
+}
+
+// a A + b B in FP64 on the union of the two block patterns
+DMat add_union(Ctx &c, const DMat &A, double a, const DMat &Bm, double b) {
+  Maps ma = build_maps(c, A.pat, false), mb = build_maps(c, Bm.pat, false);
+  Buf ub = c.alloc(sizeof(uint32_t) * (size_t)ma.nbr * ma.W);
+  launch_or_upper(c, ma.bits.as<uint32_t>(), mb.bits.as<uint32_t>(), ma.nbr, ma.W, ub.as<uint32_t>());
+  DMat o;
+  o.pat = pattern_from_bits(c, A.pat.n, ma.nbr, ma.W, ub);
+  o.pool = new_pool(c, P64, o.pat.nnzb);
+  launch_add_union(c, o.pat.row_of.as<int32_t>(), o.pat.col_idx.as<int32_t>(), o.pat.nnzb, ma.nbr, A.pool->vals.p,
+                   A.pool->prec, ma.idxmap.as<int32_t>(), a, Bm.pool->vals.p, Bm.pool->prec,
+                   mb.idxmap.as<int32_t>(), b, o.pool->vals.as<double>());
+  return o;
 }
 
 struct TruncResult {
@@ -400,6 +505,25 @@ Buf norms_of(Ctx &c, const DMat &X) {
   return nrm2;
 }
 
+// make the stored diagonal blocks of X exactly symmetric (sign 1) or
+// antisymmetric (sign -1); X must own its pool
+void sym_diag(Ctx &c, DMat &X, double sign) {
+  launch_sym_diag(c, X.pool->vals.p, X.pool->prec, X.pat.row_ptr.as<int64_t>(), X.pat.col_idx.as<int32_t>(),
+                  slot_ptr(X.pat), X.pat.nbr, sign);
+}
+
+// ||X||_F of the whole symmetric (or antisymmetric) matrix held by its upper blocks
+double frob_norm(Ctx &c, const DMat &X) {
+  if (X.pat.nnzb <= 0) return 0.0;
+  Buf nrm2 = norms_of(c, X);
+  launch_weight_offdiag(c, nrm2.as<double>(), X.pat.row_of.as<int32_t>(), X.pat.col_idx.as<int32_t>(), X.pat.nnzb);
+  Buf sum = c.alloc(sizeof(double));
+  launch_reduce_parts(c, nrm2.as<double>(), X.pat.nnzb, 1, sum.as<double>());
+  double v = 0.0;
+  c.d2h(&v, sum.p, sizeof(double));
+  return std::sqrt(std::fmax(v, 0.0));
+}
+
 // restrict X to the blocks present in mask (pattern + slots rewritten)
 void restrict_to(Ctx &c, DMat &X, const Pattern &mask) {
   Maps mm = build_maps(c, mask, false);
@@ -447,6 +571,121 @@ struct sp2_tape : public sp2::Tape {};
 namespace sp2 {
 namespace {
 
+// X with values in precision prec: a view sharing the pool when it already is
+DMat as_prec(Ctx &c, const DMat &X, int prec) {
+  if (X.pool->prec == prec) {
+    DMat d;
+    d.pat = clone_pattern(c, X.pat);
+    d.pool = X.pool;
+    return d;
+  }
+  return compact_values(c, X, prec);
+}
+
+struct CorrStats {
+  int rounds = 0;
+  double time_s = 0.0, flops = 0.0, delta_norm = 0.0, step_norm = 0.0, e_last = 0.0;
+  int64_t max_nnzb = 0;
+};
+
+// Occupied-subspace correction rounds (the operation documented with
+// sp2_options.correct): Delta = [D, [D, F]], dD = J Delta along the stored
+// X~_0 .. X~_{n-1} (derivative of the polynomial steps, blocks dropped within
+// corr_tol), D <- FP64 purification of D + dD.  The commutator C = [D, F] is
+// formed in FP64 (it is small: the difference of two O(1) products); [D, C]
+// and the derivative steps use the arithmetic the expansion used for each X~_i.
+DMat subspace_correction(Ctx &c, const DMat &F, DMat D, const std::vector<DMat> &seq, const std::vector<int> &p,
+                         const std::vector<double> &alph, double w, const sp2_options &o, int lowmode, double tau_n,
+                         CorrStats &cs) {
+  const double beta = o.corr_tol > 0.0 ? o.corr_tol : 1e-9;
+  const double fl = 2.0 * B * B * B;
+  const int n = (int)seq.size();
+  auto note = [&](const DMat &M) { cs.max_nnzb = std::max(cs.max_nnzb, M.pat.nnzb); };
+  auto drop = [&](DMat &M, const SquareOut &so) {
+    note(M);
+    Buf nrm2 = column(c, so.parts, M.pat.nnzb, 3);
+    truncate_matrix(c, M, nrm2.as<double>(), beta, SP2_TRUNC_FROB, o.coarse_bs);
+  };
+  const int lp = lowmode == M_F64 ? P64 : P32;
+  for (int r = 0; r < o.correct; ++r) {
+    // the symmetric part of D: a low-precision iterate's diagonal blocks carry
+    // antisymmetric rounding noise, which the correction must not see
+    if (r == 0) {
+      D = compact_values(c, D, D.pool->prec);
+      sym_diag(c, D, 1.0);
+    }
+    DMat D64 = as_prec(c, D, P64);
+    // C = D F - F D, antisymmetric, FP64
+    DMat C;
+    {
+      Maps mD = build_maps(c, D64.pat, true), mF = build_maps(c, F.pat, true);
+      PairOpt pc;
+      pc.neg2 = true;
+      SquareOut co = pair_product(c, D64, mD, F, mF, pc);
+      cs.flops += co.sums[4] * fl;
+      C = std::move(co.next);
+      sym_diag(c, C, -1.0);
+      drop(C, co);
+    }
+    // dX~_0 = -(D C - C D) / w = -Delta / w
+    DMat dX;
+    {
+      DMat Dl = as_prec(c, D, lp), Cl = as_prec(c, C, lp);
+      Maps mD = build_maps(c, Dl.pat, true), mC = build_maps(c, Cl.pat, true);
+      PairOpt pd;
+      pd.neg2 = true;
+      pd.yanti = true;
+      pd.cc = -1.0 / w;
+      pd.mode = lowmode;
+      pd.oprec = lp;
+      SquareOut dd = pair_product(c, Dl, mD, Cl, mC, pd);
+      cs.flops += dd.sums[4] * fl;
+      cs.delta_norm = std::sqrt(std::fmax(dd.sums[0], 0.0));  // no G: sums[0] = ||D C - C D||_F^2
+      dX = std::move(dd.next);
+      drop(dX, dd);
+    }
+    // derivative of X_{i+1} = ca I + cb X~_i + cc X~_i^2 along dX~_i
+    for (int i = 0; i < n; ++i) {
+      const DMat &Xi = seq[i];
+      const int mi = Xi.pool->prec == P32 ? lowmode : M_F64;
+      DMat G = as_prec(c, dX, Xi.pool->prec);
+      Maps mX = build_maps(c, Xi.pat, true), mG = build_maps(c, G.pat, true);
+      double ca, cb, cc;
+      poly_coeffs(p[i + 1], alph[i + 1], ca, cb, cc);
+      PairOpt pj;
+      pj.G = &G;
+      pj.mg = &mG;
+      pj.cb = cb;
+      pj.cc = cc;
+      pj.mode = mi;
+      pj.oprec = Xi.pool->prec;
+      SquareOut jo = pair_product(c, Xi, mX, G, mG, pj);
+      cs.flops += jo.sums[4] * fl;
+      dX = std::move(jo.next);
+      drop(dX, jo);
+    }
+    cs.step_norm = frob_norm(c, dX);
+    DMat P = add_union(c, D64, 1.0, dX, 1.0);
+    note(P);
+    for (int k = 0; k < o.corr_purify; ++k) {
+      double ca, cb, cc;
+      poly_coeffs(k % 2 == 0 ? 1 : 0, 1.0, ca, cb, cc);
+      Maps m = build_maps(c, P.pat, true);
+      SquareOut so = square_step(c, P, m, M_F64, P64, ca, cb, cc);
+      cs.flops += so.sums[4] * fl;
+      cs.e_last = std::sqrt(std::fmax(so.sums[0], 0.0));
+      DMat Pn = std::move(so.next);
+      note(Pn);
+      Buf nrm2 = column(c, so.parts, Pn.pat.nnzb, 3);
+      truncate_matrix(c, Pn, nrm2.as<double>(), tau_n, o.trunc_norm, o.coarse_bs);
+      P = std::move(Pn);
+    }
+    D = std::move(P);
+    cs.rounds++;
+  }
+  return D;
+}
+
 void add_checkpoint(Ctx &c, Tape &t, int i, const DMat &X) {
   auto d = std::make_shared<DMat>(compact_values(c, X, X.pool->prec));
   t.bytes += (int64_t)d->pat.nnzb * BB * (d->pool->prec == P64 ? 8 : 4);
@@ -478,7 +717,15 @@ int run_density(Ctx &c, const sp2_bsr *Fin, int64_t n_occ, double lmin, double l
     fail(SP2_ERR_INVALID_ARG, "tolerances must be >= 0");
   if (st && st->capacity < o.n_max_cap + 1) fail(SP2_ERR_INVALID_ARG, "stats capacity < n_max_cap + 1");
   if (tape_out && !o.record_tape) fail(SP2_ERR_INVALID_ARG, "a tape needs record_tape = 1");
+  if (o.correct < 0 || o.correct > 8) fail(SP2_ERR_INVALID_ARG, "correct must be in [0, 8]");
+  if (o.correct > 0 && (o.corr_purify < 1 || o.corr_purify > 16))
+    fail(SP2_ERR_INVALID_ARG, "corr_purify must be in [1, 16]");
+  if (!(o.corr_tol >= 0.0)) fail(SP2_ERR_INVALID_ARG, "corr_tol must be >= 0");
   const int lowmode = o.precision == SP2_PREC_FP32 ? M_F32 : (o.precision == SP2_PREC_BF16X3 ? M_BF16X3 : M_F64);
+  const bool corr = o.correct > 0;
+  // with the correction and no switch tolerance the whole expansion stays in
+  // the low precision and stops by its own criterion
+  const bool low_to_end = corr && !(o.switch_tol > 0.0);
 
   auto t_start = std::chrono::steady_clock::now();
   DMat F = borrow_matrix(c, Fin, "F");
@@ -520,7 +767,8 @@ int run_density(Ctx &c, const sp2_bsr *Fin, int64_t n_occ, double lmin, double l
 
   int n = -1, stop_reason = 0, status = SP2_OK;
   double alg_flops = 0.0;
-  int64_t max_nnzb = 0;
+  int64_t max_nnzb = 0, seq_bytes = 0;
+  std::vector<DMat> seq;  // X~_0 .. X~_{n-1} for the correction
   for (int i = 0;; ++i) {
     auto t_it = std::chrono::steady_clock::now();
     const int mode = X.pool->prec == P32 ? lowmode : M_F64;
@@ -561,7 +809,8 @@ int run_density(Ctx &c, const sp2_bsr *Fin, int64_t n_occ, double lmin, double l
     // the criterion compares e_i with e_{i-2}: both must come from FP64 squares
     bool stop = false;
     const bool fp64_window = mode == M_F64 && (switch_iter >= 0 && i >= switch_iter + 2);
-    if (i >= 1 && fp64_window) {
+    const bool low_window = low_to_end && mode != M_F64;
+    if (i >= 1 && (fp64_window || low_window)) {
       if (i >= std::max(sch.n_min, 2) && p[i] != p[i - 1] && e[i] > C_STOP * e[i - 2] * e[i - 2]) {
         stop = true;
         stop_reason = SP2_STOP_CRITERION;
@@ -598,6 +847,10 @@ int run_density(Ctx &c, const sp2_bsr *Fin, int64_t n_occ, double lmin, double l
     }
     p.push_back(pn);
     alph.push_back(an);
+    if (corr) {
+      seq.push_back(compact_values(c, X, X.pool->prec));
+      seq_bytes += seq.back().pat.nnzb * (int64_t)BB * (X.pool->prec == P64 ? 8 : 4);
+    }
     DMat Xn = std::move(so.next);
     const int64_t nout = Xn.pat.nnzb;
     {
@@ -607,8 +860,10 @@ int run_density(Ctx &c, const sp2_bsr *Fin, int64_t n_occ, double lmin, double l
       errM.push_back(tr.err_mixed);
       taus.push_back(sch.tau[i + 1]);
     }
-    if (Xn.pool->prec == P32 && (ei < o.switch_tol || ei < low_floor(mode, trX))) {
+    const bool to_fp64 = (o.switch_tol > 0.0 && ei < o.switch_tol) || (!low_to_end && ei < low_floor(mode, trX));
+    if (Xn.pool->prec == P32 && to_fp64) {
       Xn = compact_values(c, Xn, P64);
+      sym_diag(c, Xn, 1.0);  // the FP64 tail starts from the symmetric part
       switch_iter = i + 1;
     }
     X = std::move(Xn);
@@ -620,9 +875,29 @@ int run_density(Ctx &c, const sp2_bsr *Fin, int64_t n_occ, double lmin, double l
                    ksq[i] > 0.0 ? iflops[i] / ksq[i] / 1e12 : 0.0, mode == M_F64 ? "" : " low precision");
   }
 
+  // ---- subspace correction ---------------------------------------------------------
+  CorrStats cs;
+  if (corr) {
+    auto t_c = std::chrono::steady_clock::now();
+    X = subspace_correction(c, F, std::move(X), seq, p, alph, w, o, lowmode, taus[n], cs);
+    seq.clear();
+    c.sync();
+    cs.time_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_c).count();
+    alg_flops += cs.flops;
+    if (verbose())
+      std::fprintf(stderr, "[sp2] correction: %d round(s) %.3f s ||Delta||=%.3e ||dD||=%.3e e_last=%.3e\n", cs.rounds,
+                   cs.time_s, cs.delta_norm, cs.step_norm, cs.e_last);
+  }
+
   // ---- Step 3 and outputs ---------------------------------------------------------
   double h = NaN, l = NaN;
-  homo_lumo(sch, e, trv, p, alph, n, lmin, lmax, N, n_occ, h, l);
+  {
+    std::vector<double> unit(n + 1);
+    for (int i = 0; i <= n; ++i)
+      unit[i] = precv[i] == SP2_PREC_FP64 ? DELTA_N
+                : (precv[i] == SP2_PREC_FP32 ? 1.0 / 16777216.0 : 1.0 / 65536.0);
+    homo_lumo(sch, e, trv, p, alph, n, lmin, lmax, N, n_occ, h, l, &unit);
+  }
   double bound = NaN;
   if (sch.bounds) {
     bound = 0.0;
@@ -630,6 +905,10 @@ int run_density(Ctx &c, const sp2_bsr *Fin, int64_t n_occ, double lmin, double l
       if (errM[i] > 0.0) bound += errM[i] / (sch.xi[i] - errM[i]);
   }
   if (status == SP2_OK && std::fabs(trv[n] - (double)n_occ) > 0.5) status = SP2_WARN_TRACE;
+  if (X.pool->prec == P32) {  // a low-precision result: return its symmetric part
+    X = compact_values(c, X, P32);
+    sym_diag(c, X, 1.0);
+  }
   *D_out = export_bsr(c, X);
   const double elapsed = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
   if (hest) *hest = h;
@@ -648,6 +927,14 @@ int run_density(Ctx &c, const sp2_bsr *Fin, int64_t n_occ, double lmin, double l
     st->max_nnzb = max_nnzb;
     st->square_time_total_s = 0.0;
     for (int i = 0; i <= n; ++i) st->square_time_total_s += ksq[i];
+    st->corr_rounds = cs.rounds;
+    st->corr_time_s = cs.time_s;
+    st->corr_flops = cs.flops;
+    st->corr_delta_norm = cs.delta_norm;
+    st->corr_step_norm = cs.step_norm;
+    st->corr_e_last = cs.e_last;
+    st->corr_max_nnzb = cs.max_nnzb;
+    st->seq_bytes = seq_bytes;
     for (int i = 0; i <= n; ++i) {
       if (st->square_time_s) st->square_time_s[i] = ksq[i];
       if (st->e) st->e[i] = e[i];
@@ -694,40 +981,22 @@ DMat checkpoint_copy(const Tape &t, int i) {
   return d;
 }
 
-DMat as_f64(Ctx &c, const DMat &X) {
-  if (X.pool->prec == P64) {
-    DMat d;
-    d.pat = clone_pattern(c, X.pat);
-    d.pool = X.pool;
-    return d;
-  }
-  return compact_values(c, X, P64);
-}
 
-// out = cb G + cc (G X + X G) on the pattern outpat
-DMat anticommutator(Ctx &c, const DMat &G, const DMat &X, const Pattern &outpat, double cb, double cc) {
+// out = cb G + cc (G X + X G) on the pattern outpat, in the arithmetic of mode
+// (FP64, or FP32 values for the FP32 / BF16x3 products)
+DMat anticommutator(Ctx &c, const DMat &Gin, const DMat &Xin, const Pattern &outpat, double cb, double cc, int mode) {
+  const int prec = mode == M_F64 ? P64 : P32;
+  DMat G = as_prec(c, Gin, prec), X = as_prec(c, Xin, prec);
   Maps mg = build_maps(c, G.pat, false), mx = build_maps(c, X.pat, false);
-  DMat o;
-  o.pat = clone_pattern(c, outpat);
-  o.pat.slot.reset();
-  o.pool = new_pool(c, P64, o.pat.nnzb);
-  AntiArgs a;
-  a.gpool = G.pool->vals.as<double>();
-  a.gidxmap = mg.idxmap.as<int32_t>();
-  a.gbits = mg.bits.as<uint32_t>();
-  a.xpool = X.pool->vals.as<double>();
-  a.xidxmap = mx.idxmap.as<int32_t>();
-  a.xbits = mx.bits.as<uint32_t>();
-  a.nbr = G.pat.nbr;
-  a.W = mg.W;
-  a.out_row = o.pat.row_of.as<int32_t>();
-  a.out_col = o.pat.col_idx.as<int32_t>();
-  a.nout = o.pat.nnzb;
-  a.opool = o.pool->vals.as<double>();
-  a.cb = cb;
-  a.cc = cc;
-  launch_anticommutator(c, a);
-  return o;
+  PairOpt po;
+  po.G = &G;
+  po.mg = &mg;
+  po.cb = cb;
+  po.cc = cc;
+  po.mode = mode;
+  po.oprec = prec;
+  po.outpat = &outpat;
+  return std::move(pair_product(c, X, mx, G, mg, po).next);
 }
 
 int last_ckpt_at_or_below(const Tape &t, int i) {
@@ -760,9 +1029,8 @@ sp2_bsr *run_vjp(Ctx &c, const Tape &t, const sp2_bsr *Win) {
       seg_lo = c0;
       seg_hi = i - 1;
     }
-    const DMat X = as_f64(c, seg[(i - 1) - seg_lo]);
     const TapeIter &ti = t.it[i];
-    Xbar = anticommutator(c, Xbar, X, t.it[i - 1].mask, ti.cb, ti.cc);
+    Xbar = anticommutator(c, Xbar, seg[(i - 1) - seg_lo], t.it[i - 1].mask, ti.cb, ti.cc, t.it[i - 1].mode);
     if (i - 1 < seg_hi) seg.resize((i - 1) - seg_lo + 1);  // drop X~ no longer needed
     seg_hi = i - 1;
   }
@@ -782,8 +1050,7 @@ sp2_bsr *run_jvp(Ctx &c, const Tape &t, const sp2_bsr *dFin) {
   DMat X = checkpoint_copy(t, 0);
   for (int i = 1; i <= t.n_iter; ++i) {
     const TapeIter &ti = t.it[i];
-    const DMat X64 = as_f64(c, X);
-    DMat nd = anticommutator(c, dX, X64, ti.mask, ti.cb, ti.cc);
+    DMat nd = anticommutator(c, dX, X, ti.mask, ti.cb, ti.cc, t.it[i - 1].mode);
     dX = std::move(nd);
     if (i < t.n_iter) X = replay_step(c, t, i, X);
   }
@@ -844,6 +1111,9 @@ void sp2_options_default(sp2_options *o) {
   o->idem_stop = 0.0;
   o->record_tape = 0;
   o->n_checkpoints = 0;
+  o->correct = 0;
+  o->corr_purify = 2;
+  o->corr_tol = 1e-9;
 }
 
 int sp2_create(sp2_ctx **ctx, int device, void *hip_stream) {
@@ -1025,6 +1295,56 @@ int sp2_square_step(sp2_ctx *ctx, const sp2_bsr *Xin, double a, double b, double
       sums[3] = so.sums[4] * 2.0 * B * B * B;
     }
     *Xn_out = export_bsr(*ctx, so.next);
+    return SP2_OK;
+  });
+}
+
+int sp2_pair_product(sp2_ctx *ctx, const sp2_bsr *Xin, const sp2_bsr *Yin, const sp2_bsr *Gin, int sign, int y_antisym,
+                     double a, double b, double cc, int precision, sp2_bsr **out, double sums[2]) {
+  return guarded(ctx, [&]() {
+    if (!out) fail(SP2_ERR_INVALID_ARG, "NULL output");
+    *out = nullptr;
+    if (precision < 0 || precision > 2) fail(SP2_ERR_INVALID_ARG, "unknown precision");
+    if (sign != 1 && sign != -1) fail(SP2_ERR_INVALID_ARG, "sign must be +1 or -1");
+    if (y_antisym != 0 && y_antisym != 1) fail(SP2_ERR_INVALID_ARG, "y_antisym must be 0 or 1");
+    DMat X = borrow_matrix(*ctx, Xin, "X");
+    DMat Y = borrow_matrix(*ctx, Yin, "Y");
+    if (Xin->n != Yin->n) fail(SP2_ERR_INVALID_ARG, "X and Y differ in size");
+    check_finite(*ctx, Xin->val, Xin->nnzb * (int64_t)BB, "X");
+    check_finite(*ctx, Yin->val, Yin->nnzb * (int64_t)BB, "Y");
+    DMat G;
+    if (Gin) {
+      G = borrow_matrix(*ctx, Gin, "G");
+      if (Gin->n != Xin->n) fail(SP2_ERR_INVALID_ARG, "G differs in size");
+      check_finite(*ctx, Gin->val, Gin->nnzb * (int64_t)BB, "G");
+    }
+    int mode = M_F64;
+    if (precision != SP2_PREC_FP64) {
+      X = compact_values(*ctx, X, P32);
+      Y = compact_values(*ctx, Y, P32);
+      if (Gin) G = compact_values(*ctx, G, P32);
+      mode = precision == SP2_PREC_FP32 ? M_F32 : M_BF16X3;
+    }
+    Maps mx = build_maps(*ctx, X.pat, true), my = build_maps(*ctx, Y.pat, true);
+    Maps mg;
+    if (Gin) mg = build_maps(*ctx, G.pat, false);
+    PairOpt po;
+    po.neg2 = sign < 0;
+    po.yanti = y_antisym != 0;
+    po.G = Gin ? &G : nullptr;
+    po.mg = Gin ? &mg : nullptr;
+    po.ca = a;
+    po.cb = b;
+    po.cc = cc;
+    po.mode = mode;
+    po.oprec = X.pool->prec;
+    SquareOut so = pair_product(*ctx, X, mx, Y, my, po);
+    if (sums) {
+      sums[0] = frob_norm(*ctx, so.next);
+      sums[0] *= sums[0];
+      sums[1] = so.sums[4] * 2.0 * B * B * B;
+    }
+    *out = export_bsr(*ctx, so.next);
     return SP2_OK;
   });
 }

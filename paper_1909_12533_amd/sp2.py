@@ -213,6 +213,7 @@ class DensityResult:
     alg_flops: float
     max_nnzb: int
     square_time_s: float = 0.0
+    correction: dict = field(default_factory=dict)
     iters: dict = field(default_factory=dict)
     tape: "Tape | None" = None
 
@@ -298,7 +299,11 @@ def density(F: BsrMatrix, n_occ: int, lmin: float, lmax: float, homo_ub=None, lu
                          n_min=int(st.n_min), stop_reason=_STOP.get(int(st.stop_reason), "?"),
                          switch_iter=int(st.switch_iter), subspace_err_bound=float(st.subspace_err_bound),
                          time_s=float(st.time_s), alg_flops=float(st.alg_flops), max_nnzb=int(st.max_nnzb),
-                         square_time_s=float(st.square_time_total_s), iters=iters, tape=Tape(ctx, tape_h) if o.record_tape else None)
+                         square_time_s=float(st.square_time_total_s),
+                         correction={k: getattr(st, k) for k in ("corr_rounds", "corr_time_s", "corr_flops",
+                                                                 "corr_delta_norm", "corr_step_norm", "corr_e_last",
+                                                                 "corr_max_nnzb", "seq_bytes")},
+                         iters=iters, tape=Tape(ctx, tape_h) if o.record_tape else None)
 
 
 def square_step(X: BsrMatrix, a: float, b: float, c: float, precision="fp64", ctx: Context | None = None):
@@ -310,6 +315,24 @@ def square_step(X: BsrMatrix, a: float, b: float, c: float, precision="fp64", ct
     s = X._struct()
     p = _PREC[precision] if isinstance(precision, str) else int(precision)
     ctx._check(ctx.lib.sp2_square_step(ctx.h, C.byref(s), float(a), float(b), float(c), p, C.byref(out), sums))
+    r = ctx.take(out)
+    ctx.trim()
+    return r, list(sums)
+
+
+def pair_product(X: BsrMatrix, Y: BsrMatrix, G: BsrMatrix | None = None, sign=1, y_antisym=False, a=0.0, b=0.0,
+                 c=1.0, precision="fp64", ctx: Context | None = None):
+    """a I + b G + c (X Y + sign Y X) on the block pattern of X Y + Y X;
+    returns (out, [||out||_F^2, flops]); see sp2_pair_product in sp2dm.h."""
+    ctx = ctx or context(X.device.index)
+    out = C.POINTER(L.sp2_bsr)()
+    sums = (C.c_double * 2)()
+    sx, sy = X._struct(), Y._struct()
+    sg = G._struct() if G is not None else None
+    p = _PREC[precision] if isinstance(precision, str) else int(precision)
+    ctx._check(ctx.lib.sp2_pair_product(ctx.h, C.byref(sx), C.byref(sy), C.byref(sg) if sg is not None else None,
+                                        int(sign), int(bool(y_antisym)), float(a), float(b), float(c), p,
+                                        C.byref(out), sums))
     r = ctx.take(out)
     ctx.trim()
     return r, list(sums)
