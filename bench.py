@@ -72,6 +72,43 @@ def cpu_baseline(L=12, tau=1e-6):
     }
 
 
+KERNEL_SOURCES = ["paper_1909_12533_amd/csrc/kernels_tile.hip", "paper_1909_12533_amd/csrc/mfma.h"]
+
+
+def kernel_source_hash():
+    import hashlib
+
+    h = hashlib.sha256()
+    root = os.path.dirname(os.path.abspath(__file__))
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(root, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def traffic_per_launch(prec, L):
+    """HBM bytes per launch of the FP64 square from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE summary of this workload, each counter scaled by
+    what it read for a 1 GiB device copy in the same run; None when there is no
+    summary for this kernel and workload or the kernel sources changed since the
+    counters were taken."""
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
+                        f"k_square_tile_{prec}_lattice{L}_pmc.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as fh:
+        for line in fh:
+            parts = line.split()
+            if len(parts) == 2 and not line.startswith("#"):
+                kv[parts[0]] = parts[1]
+    if kv.get("source_sha256") != kernel_source_hash():
+        return None
+    kib = float(kv["fetch_kib_per_launch"]) * float(kv["fetch_factor"]) + \
+        float(kv["write_kib_per_launch"]) * float(kv["write_factor"])
+    return round(kib * 1024.0)
+
+
 def bsr_diff_frobenius(A, B):
     """||A - B||_F of two symmetric upper-BSR device matrices (blocks matched
     by (I, J); off-diagonal blocks count twice for their mirrors)."""
@@ -107,9 +144,11 @@ def main():
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="copy a buffer of this size once before timing (reference for HBM traffic counters)")
     ap.add_argument("--correct", type=int, default=None,
-                    help="subspace-correction rounds (default: 0 for fp64, 1 for fp32, 2 for bf16x3)")
+                    help="subspace-correction rounds (default: 0 for fp64, 1 for fp32 / bf16x3)")
     ap.add_argument("--corr-tol", type=float, default=None,
                     help="Frobenius budget for dropping blocks of the correction's intermediates (library default)")
+    ap.add_argument("--compare", default="bf16x3", choices=["none", "fp32", "bf16x3"],
+                    help="with --precision fp64: one mixed run (with and without the correction) for speedup / error")
     ap.add_argument("--switch-tol", type=float, default=None,
                     help="FP64 tail once ||X - X^2||_F < this (default: 0 with the correction, else 1e-3)")
     ap.add_argument("--bounds", default=None,
@@ -156,7 +195,7 @@ def main():
         log(f"calibration copy: {nb} bytes read, {nb} bytes written")
         del src, dst
 
-    correct = args.correct if args.correct is not None else {"fp64": 0, "fp32": 1, "bf16x3": 2}[prec]
+    correct = args.correct if args.correct is not None else (0 if prec == "fp64" else 1)
     switch_tol = args.switch_tol if args.switch_tol is not None else (0.0 if correct else 1e-3)
     mopts = dict(precision=prec, correct=correct, switch_tol=switch_tol) if prec != "fp64" else dict(correct=correct)
     if args.corr_tol is not None:
@@ -178,9 +217,9 @@ def main():
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         times.append(dt)
-        flops.append(res.alg_flops)
+        flops.append(res.alg_flops - res.correction["corr_flops"])  # the expansion's own block products
         ksq.append(res.square_time_s)
-        log(f"step {k}: n={res.n_iter} {dt:.3f} s  {res.alg_flops / dt / 1e12:.2f} TFLOP/s  "
+        log(f"step {k}: n={res.n_iter} {dt:.3f} s  {flops[-1] / dt / 1e12:.2f} TFLOP/s  "
             f"square kernels {res.square_time_s:.3f} s")
         if k == 0:
             it = res.iters
@@ -198,6 +237,26 @@ def main():
     sel = res.iters["precision"] == code
     achieved = float(res.iters["iter_flops"][sel].sum() / res.iters["square_time_s"][sel].sum() / 1e12)
     mixed = {}
+    if prec == "fp64" and args.compare != "none":
+        t_ref = sum(times) / len(times)
+        for cor in (1, 0):
+            mo = dict(precision=args.compare, correct=cor, switch_tol=0.0 if cor else 1e-3)
+            if cor and args.corr_tol is not None:
+                mo["corr_tol"] = args.corr_tol
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            rm = sp2.density(F, no, lmin, lmax, hub, llb, **mo, **opts)
+            torch.cuda.synchronize()
+            dtm = time.perf_counter() - t0
+            err = bsr_diff_frobenius(rm.D, res.D)
+            key = args.compare + ("+correction" if cor else "+fp64_tail")
+            mixed[key] = {"time_to_D_s": round(dtm, 4), "speedup_vs_fp64": round(t_ref / dtm, 4),
+                          "err_vs_fp64_D": err, "n_iter": rm.n_iter, "switch_iter": rm.switch_iter,
+                          "correction": rm.correction}
+            log(f"mixed {key}: {dtm:.3f} s, speedup {t_ref / dtm:.2f}x, ||D - D_fp64||_F = {err:.3e}, "
+                f"correction {rm.correction}")
+            del rm
+        mixed = {"mixed": mixed}
     if prec != "fp64":
         ref = sp2.density(F, no, lmin, lmax, hub, llb, precision="fp64", **opts)
         err = bsr_diff_frobenius(res.D, ref.D)
@@ -233,10 +292,11 @@ def main():
             "alg_tflop_per_step": round(res.alg_flops / 1e12, 3),
         },
         "checks": {"trace_err": abs(trD - no), "e_n": float(res.iters["e"][-1]),
-                   "homo_est": res.homo_est, "lumo_est": res.lumo_est, **mixed},
+                   "homo_est": None if math.isnan(res.homo_est) else res.homo_est,
+                   "lumo_est": None if math.isnan(res.lumo_est) else res.lumo_est, **mixed},
         "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK[prec], "unit": "TFLOP/s",
-                     "frac": round(achieved / PEAK[prec], 4), "traffic": None,
-                     "kernel": "k_square (MFMA block-sparse symmetric square + fused epilogue)"},
+                     "frac": round(achieved / PEAK[prec], 4), "traffic": traffic_per_launch(prec, L),
+                     "kernel": "k_square_tile (MFMA block-sparse symmetric square + fused epilogue)"},
     }
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)...")

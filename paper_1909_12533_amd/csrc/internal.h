@@ -198,6 +198,7 @@ struct TileArgs {
   int npass = 1;           // 1: X Y; 2: X Y + s2 Y X
   int neg2 = 0;            // s2 = -1
   int xanti = 0, yanti = 0;
+  const void *xpack = nullptr, *ypack = nullptr;  // BF16x3: operands split into bf16 images (launch_pack_bf16x3)
   const void *gpool;       // G of the cb term (same precision as X), or null
   const int32_t *gidxmap;
   int nbr, W;
@@ -214,6 +215,9 @@ struct TileArgs {
 int64_t build_tiles(Ctx &c, const int32_t *oidx, int nbr, Buf &tiles);
 void launch_square_tile(Ctx &c, int mode, const TileArgs &a);
 void launch_square_tile_bf16x3(Ctx &c, const TileArgs &a);  // kernels_bf16x3.hip
+// split the stored blocks of an FP32 pool into bf16 hi/lo images of the block
+// and of its transpose: packed[slot] = 4 x 4096 bf16 (32 KB per pool slot)
+void launch_pack_bf16x3(Ctx &c, const float *pool, const int32_t *slot, int64_t nblocks, uint16_t *packed);
 
 // truncation (kernels_trunc.hip)
 struct TruncOut {

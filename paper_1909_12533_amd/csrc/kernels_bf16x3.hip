@@ -5,15 +5,21 @@
 // v_mfma_f32_16x16x32_bf16 with FP32 accumulation (the dropped lo*lo term and
 // the residual x - hi - lo are both of relative size ~2^-16).
 //
+// The split is done once per operand matrix by k_pack_bf16x3, which writes
+// every stored block S as four bf16 planes: N = S (row-major) and T = S^T,
+// each as hi and lo.  An MFMA operand wants 8 consecutive k of one row (A) or
+// one column (B) in a single 16-byte LDS read, i.e. k-contiguous rows:
+//   A = X_{I,K}: rows of S = X_IK (image N) when I <= K, of S = X_KI^T
+//                (image T) when I > K;
+//   B = X_{K,J}: stored as [column][k]: image T of S = X_KJ when K <= J,
+//                image N of S = X_JK when K > J.
+// So every staging load is a contiguous 16 KB copy (hi and lo planes of one
+// image) and the tile kernel does no conversion arithmetic.
+//
 // Same work decomposition as k_square_tile (one workgroup per 2 x 2 output
-// tile, one 64 x 64 output block per wave).  The split happens once per
-// element while staging: the four operand blocks of a K are loaded as FP32,
-// split in registers and written to LDS as two bf16 planes each, always
-// k-contiguous (A as [row][k], B as [column][k]) so that every MFMA operand
-// (8 consecutive k of one row/column) is a single 16-byte LDS read.  Operands
-// whose k index runs along the stored rows are loaded as 4-row column chunks
-// (4-byte loads, coalesced along the column index) so that their transposed
-// LDS write is still one 8-byte store per plane.
+// tile, one 64 x 64 output block per wave); the workgroup needs 72 KB of LDS
+// and at most 256 registers per lane, so two workgroups share a CU and one's
+// staging overlaps the other's MFMAs.
 #include "mfma.h"
 
 namespace sp2 {
@@ -24,35 +30,47 @@ using namespace dev;
 
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
-typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 
-constexpr int LDH = 72;           // bf16 per plane row (64 + 8 pad): 144-byte rows
-constexpr int PLANE = 64 * LDH;   // bf16 per plane
+constexpr int LDH = 72;            // bf16 per LDS plane row (64 + 8 pad): 144-byte rows
+constexpr int PLANE = 64 * LDH;    // bf16 per LDS plane
+constexpr int IMG_Q = 1024;        // 16-byte chunks per image (hi + lo planes, 2 x 8 KB)
+constexpr int BLK_Q = 2 * IMG_Q;   // 16-byte chunks per packed block (images N, T)
 
 __device__ inline uint32_t bf16_rne(float x) {
   const uint32_t u = __float_as_uint(x);
   return (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;
 }
 
-// split four FP32 values into packed bf16 hi and lo pairs
-__device__ inline void split4(u32x4 v, u32x2 &hi, u32x2 &lo) {
-  uint32_t h[4], l[4];
-#pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const float x = __uint_as_float(v[j]);
-    h[j] = bf16_rne(x);
-    l[j] = bf16_rne(x - __uint_as_float(h[j] << 16));
-  }
-  hi = u32x2{h[0] | (h[1] << 16), h[2] | (h[3] << 16)};
-  lo = u32x2{l[0] | (l[1] << 16), l[2] | (l[3] << 16)};
-}
-
 __device__ inline f4 mfma_bf16(u32x4 a, u32x4 b, f4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, a), __builtin_bit_cast(bf8, b), c, 0, 0, 0);
 }
 
+// One workgroup per stored block b: packed[slot] = N_hi, N_lo, T_hi, T_lo
+// (4096 bf16 each).  The block goes through LDS so that both images are
+// written with consecutive threads on consecutive elements.
+__global__ __launch_bounds__(TPB) void k_pack_bf16x3(const float *pool, const int32_t *slot, int64_t nblocks,
+                                                     uint16_t *packed) {
+  __shared__ float t[64][65];
+  const int64_t b = blockIdx.x;
+  if (b >= nblocks) return;
+  const int64_t s = slot ? slot[b] : b;
+  const float *src = pool + s * BB;
+  for (int e = threadIdx.x; e < BB; e += TPB) t[e >> 6][e & 63] = src[e];
+  __syncthreads();
+  uint16_t *dst = packed + s * (int64_t)(4 * BB);
+  for (int e = threadIdx.x; e < BB; e += TPB) {
+    const int r = e >> 6, c = e & 63;
+    const float xn = t[r][c], xt = t[c][r];
+    const uint32_t hn = bf16_rne(xn), ht = bf16_rne(xt);
+    dst[e] = (uint16_t)hn;
+    dst[BB + e] = (uint16_t)bf16_rne(xn - __uint_as_float(hn << 16));
+    dst[2 * BB + e] = (uint16_t)ht;
+    dst[3 * BB + e] = (uint16_t)bf16_rne(xt - __uint_as_float(ht << 16));
+  }
+}
+
 template <typename TO, bool GEN>
-__global__ __launch_bounds__(TPB, 1) void k_square_tile_bf16x3(TileArgs a) {
+__global__ __launch_bounds__(TPB, 2) void k_square_tile_bf16x3(TileArgs a) {
   // operand o (A0, A1, B0, B1) x plane (hi, lo)
   __shared__ __align__(16) uint16_t L[4][2][PLANE];
   const int64_t t = xcd_tile(a);
@@ -66,8 +84,8 @@ __global__ __launch_bounds__(TPB, 1) void k_square_tile_bf16x3(TileArgs a) {
   const bool has_i1 = I0 + 1 < nbr, has_j1 = J0 + 1 < nbr;
   int32_t pos = -1;
   if (I < nbr && J < nbr && I <= J) pos = __builtin_amdgcn_readfirstlane(a.oidx[(int64_t)I * nbr + J]);
-  const float *xp = static_cast<const float *>(a.xpool);
-  const float *yp = static_cast<const float *>(GEN ? a.ypool : a.xpool);
+  const u32x4 *xq = static_cast<const u32x4 *>(a.xpack);
+  const u32x4 *yq = static_cast<const u32x4 *>(GEN ? a.ypack : a.xpack);
 
   f4 acc[4][4];
 #pragma unroll
@@ -104,77 +122,52 @@ __global__ __launch_bounds__(TPB, 1) void k_square_tile_bf16x3(TileArgs a) {
     return K;
   };
 
-  // staged FP32 values of the four operands, 16 per thread each
+  // staged images of the four operands, 4 chunks of 16 bytes per thread each
   u32x4 r0[4], r1[4], r2[4], r3[4];
   int32_t s0 = -1, s1 = -1, s2 = -1, s3 = -1;
-  bool k0 = true, k1 = true, k2 = true, k3 = true;  // k runs along the stored columns
-  const float *p0 = xp, *p1 = xp, *p2 = yp, *p3 = yp;  // source pools of the staged blocks
-  uint32_t g0 = 0u, g1 = 0u, g2 = 0u, g3 = 0u;         // sign bit to flip per staged block
-  constexpr uint32_t SGN = 0x80000000u;
-  const int cc = tid & 63, rg = tid >> 6;
-// row chunks (k along stored columns): 16-byte loads; column chunks: rows 16 rg + 4 jj + j of column cc
-#define SP2_LOAD(R, P, SL, KCOL)                                                                   \
-  do {                                                                                             \
-    if ((SL) >= 0) {                                                                               \
-      const float *blk_ = (P) + (int64_t)(SL) * BB;                                                \
-      if (KCOL) {                                                                                  \
-        const u32x4 *p_ = reinterpret_cast<const u32x4 *>(blk_) + tid;                             \
-        _Pragma("unroll") for (int j = 0; j < 4; ++j) R[j] = p_[j * TPB];                          \
-      } else {                                                                                     \
-        const uint32_t *p_ = reinterpret_cast<const uint32_t *>(blk_) + cc;                        \
-        _Pragma("unroll") for (int jj = 0; jj < 4; ++jj) {                                         \
-          const int r_ = 16 * rg + 4 * jj;                                                         \
-          R[jj] = u32x4{p_[(r_ + 0) * 64], p_[(r_ + 1) * 64], p_[(r_ + 2) * 64], p_[(r_ + 3) * 64]}; \
-        }                                                                                          \
-      }                                                                                            \
-    }                                                                                              \
+  uint32_t g0 = 0u, g1 = 0u, g2 = 0u, g3 = 0u;  // 0x80008000 to negate a staged block
+  constexpr uint32_t SGN2 = 0x80008000u;
+// image N (NIMG) or T of the block in slot SL; chunk j * 256 + tid of the image
+#define SP2_LOAD(R, Q, SL, NIMG)                                                    \
+  do {                                                                              \
+    if ((SL) >= 0) {                                                                \
+      const u32x4 *img_ = (Q) + (int64_t)(SL) * BLK_Q + ((NIMG) ? 0 : IMG_Q) + tid; \
+      _Pragma("unroll") for (int j = 0; j < 4; ++j) R[j] = img_[j * TPB];           \
+    }                                                                               \
   } while (0)
-#define SP2_ISSUE(KK, KP)                                                                  \
-  do {                                                                                     \
-    const int32_t *li_ = (GEN && (KP)) ? a.yidxmap : a.idxmap;                             \
-    const int32_t *ri_ = GEN ? ((KP) ? a.idxmap : a.yidxmap) : a.idxmap;                   \
-    p0 = p1 = (GEN && (KP)) ? yp : xp;                                                     \
-    p2 = p3 = (GEN && (KP)) ? xp : yp;                                                     \
-    s0 = __builtin_amdgcn_readfirstlane(li_[(int64_t)I0 * nbr + (KK)]);                    \
-    s1 = has_i1 ? __builtin_amdgcn_readfirstlane(li_[(int64_t)(I0 + 1) * nbr + (KK)]) : -1; \
-    s2 = __builtin_amdgcn_readfirstlane(ri_[(int64_t)(KK) * nbr + J0]);                    \
-    s3 = has_j1 ? __builtin_amdgcn_readfirstlane(ri_[(int64_t)(KK) * nbr + J0 + 1]) : -1;  \
-    k0 = I0 <= (KK);                                                                       \
-    k1 = I0 + 1 <= (KK);                                                                   \
-    k2 = (KK) > J0;                                                                        \
-    k3 = (KK) > J0 + 1;                                                                    \
-    if (GEN) {                                                                             \
-      const bool la_ = (KP) ? a.yanti : a.xanti, ra_ = (KP) ? a.xanti : a.yanti;           \
-      const bool ng_ = (KP) && a.neg2;                                                     \
-      g0 = ((la_ && !k0) != ng_) ? SGN : 0u;                                               \
-      g1 = ((la_ && !k1) != ng_) ? SGN : 0u;                                               \
-      g2 = (ra_ && k2) ? SGN : 0u;                                                         \
-      g3 = (ra_ && k3) ? SGN : 0u;                                                         \
-    }                                                                                      \
-    SP2_LOAD(r0, p0, s0, k0);                                                              \
-    SP2_LOAD(r1, p1, s1, k1);                                                              \
-    SP2_LOAD(r2, p2, s2, k2);                                                              \
-    SP2_LOAD(r3, p3, s3, k3);                                                              \
+#define SP2_ISSUE(KK, KP)                                                                    \
+  do {                                                                                       \
+    const int32_t *li_ = (GEN && (KP)) ? a.yidxmap : a.idxmap;                               \
+    const int32_t *ri_ = GEN ? ((KP) ? a.idxmap : a.yidxmap) : a.idxmap;                     \
+    const u32x4 *lq_ = (GEN && (KP)) ? yq : xq, *rq_ = (GEN && (KP)) ? xq : yq;              \
+    s0 = __builtin_amdgcn_readfirstlane(li_[(int64_t)I0 * nbr + (KK)]);                      \
+    s1 = has_i1 ? __builtin_amdgcn_readfirstlane(li_[(int64_t)(I0 + 1) * nbr + (KK)]) : -1;   \
+    s2 = __builtin_amdgcn_readfirstlane(ri_[(int64_t)(KK) * nbr + J0]);                      \
+    s3 = has_j1 ? __builtin_amdgcn_readfirstlane(ri_[(int64_t)(KK) * nbr + J0 + 1]) : -1;    \
+    const bool n0_ = I0 <= (KK), n1_ = I0 + 1 <= (KK), n2_ = (KK) > J0, n3_ = (KK) > J0 + 1; \
+    if (GEN) {                                                                               \
+      const bool la_ = (KP) ? a.yanti : a.xanti, ra_ = (KP) ? a.xanti : a.yanti;             \
+      const bool ng_ = (KP) && a.neg2;                                                       \
+      g0 = ((la_ && !n0_) != ng_) ? SGN2 : 0u;                                               \
+      g1 = ((la_ && !n1_) != ng_) ? SGN2 : 0u;                                               \
+      g2 = (ra_ && n2_) ? SGN2 : 0u;                                                         \
+      g3 = (ra_ && n3_) ? SGN2 : 0u;                                                         \
+    }                                                                                        \
+    SP2_LOAD(r0, lq_, s0, n0_);                                                              \
+    SP2_LOAD(r1, lq_, s1, n1_);                                                              \
+    SP2_LOAD(r2, rq_, s2, n2_);                                                              \
+    SP2_LOAD(r3, rq_, s3, n3_);                                                              \
   } while (0)
-// split and write one operand into its two planes, k-contiguous
-#define SP2_STORE(R, SL, KCOL, O, G)                                                              \
-  do {                                                                                            \
-    if ((SL) >= 0) {                                                                              \
-      uint16_t *ph_ = L[O][0], *pl_ = L[O][1];                                                    \
-      _Pragma("unroll") for (int j = 0; j < 4; ++j) {                                             \
-        u32x2 hi_, lo_;                                                                           \
-        split4(GEN ? (R[j] ^ u32x4{(G), (G), (G), (G)}) : R[j], hi_, lo_);                        \
-        int off_;                                                                                 \
-        if (KCOL) {                                                                               \
-          const int e_ = (j * TPB + tid) * 4;                                                     \
-          off_ = (e_ >> 6) * LDH + (e_ & 63);                                                     \
-        } else {                                                                                  \
-          off_ = cc * LDH + 16 * rg + 4 * j;                                                      \
-        }                                                                                         \
-        *reinterpret_cast<u32x2 *>(ph_ + off_) = hi_;                                             \
-        *reinterpret_cast<u32x2 *>(pl_ + off_) = lo_;                                             \
-      }                                                                                           \
-    }                                                                                             \
+// chunk j * 256 + tid: plane j / 2, row ((j & 1) * 256 + tid) / 8, 16-byte column chunk tid % 8
+#define SP2_STORE(R, SL, O, G)                                                           \
+  do {                                                                                   \
+    if ((SL) >= 0) {                                                                     \
+      _Pragma("unroll") for (int j = 0; j < 4; ++j) {                                    \
+        const int pq_ = ((j & 1) << 8) + tid;                                            \
+        uint16_t *d_ = &L[O][j >> 1][(pq_ >> 3) * LDH + (pq_ & 7) * 8];                   \
+        *reinterpret_cast<u32x4 *>(d_) = GEN ? (R[j] ^ u32x4{(G), (G), (G), (G)}) : R[j]; \
+      }                                                                                  \
+    }                                                                                    \
   } while (0)
 
   const int l16 = lane & 15, g = lane >> 4;
@@ -184,40 +177,39 @@ __global__ __launch_bounds__(TPB, 1) void k_square_tile_bf16x3(TileArgs a) {
   while (K >= 0) {
     const int32_t c0 = s0, c1 = s1, c2 = s2, c3 = s3;
     __syncthreads();  // previous planes fully consumed
-    SP2_STORE(r0, c0, k0, 0, g0);
-    SP2_STORE(r1, c1, k1, 1, g1);
-    SP2_STORE(r2, c2, k2, 2, g2);
-    SP2_STORE(r3, c3, k3, 3, g3);
+    SP2_STORE(r0, c0, 0, g0);
+    SP2_STORE(r1, c1, 1, g1);
+    SP2_STORE(r2, c2, 2, g2);
+    SP2_STORE(r3, c3, 3, g3);
     __syncthreads();
     const int Kn = next_k();
-    if (Kn >= 0) SP2_ISSUE(Kn, kpass);  // next K's blocks in flight during the MFMAs
+    if (Kn >= 0) SP2_ISSUE(Kn, kpass);  // next K's images in flight during the MFMAs
     const int32_t sa = ia ? c1 : c0, sb = jb ? c3 : c2;
     if (pos >= 0 && sa >= 0 && sb >= 0) {
       const uint16_t *ah = L[ia][0], *al = L[ia][1], *bh = L[2 + jb][0], *bl = L[2 + jb][1];
 #pragma unroll
       for (int ks = 0; ks < 64; ks += 32) {
-        u32x4 fah[4], fal[4], fbh[4], fbl[4];
+        u32x4 fbh[4], fbl[4];
+#pragma unroll
+        for (int n = 0; n < 4; ++n) {
+          const int o = (16 * n + l16) * LDH + ks + 8 * g;
+          fbh[n] = *reinterpret_cast<const u32x4 *>(bh + o);
+          fbl[n] = *reinterpret_cast<const u32x4 *>(bl + o);
+        }
+        // per A tile: the four accumulators of its row take lo*hi, then
+        // hi*lo, then hi*hi (four independent MFMAs between dependent ones)
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
           const int o = (16 * m + l16) * LDH + ks + 8 * g;
-          fah[m] = *reinterpret_cast<const u32x4 *>(ah + o);
-          fal[m] = *reinterpret_cast<const u32x4 *>(al + o);
-          fbh[m] = *reinterpret_cast<const u32x4 *>(bh + o);
-          fbl[m] = *reinterpret_cast<const u32x4 *>(bl + o);
+          const u32x4 fah = *reinterpret_cast<const u32x4 *>(ah + o);
+          const u32x4 fal = *reinterpret_cast<const u32x4 *>(al + o);
+#pragma unroll
+          for (int n = 0; n < 4; ++n) acc[m][n] = mfma_bf16(fal, fbh[n], acc[m][n]);
+#pragma unroll
+          for (int n = 0; n < 4; ++n) acc[m][n] = mfma_bf16(fah, fbl[n], acc[m][n]);
+#pragma unroll
+          for (int n = 0; n < 4; ++n) acc[m][n] = mfma_bf16(fah, fbh[n], acc[m][n]);
         }
-        // small products first, each accumulator touched once per sweep
-#pragma unroll
-        for (int m = 0; m < 4; ++m)
-#pragma unroll
-          for (int n = 0; n < 4; ++n) acc[m][n] = mfma_bf16(fal[m], fbh[n], acc[m][n]);
-#pragma unroll
-        for (int m = 0; m < 4; ++m)
-#pragma unroll
-          for (int n = 0; n < 4; ++n) acc[m][n] = mfma_bf16(fah[m], fbl[n], acc[m][n]);
-#pragma unroll
-        for (int m = 0; m < 4; ++m)
-#pragma unroll
-          for (int n = 0; n < 4; ++n) acc[m][n] = mfma_bf16(fah[m], fbh[n], acc[m][n]);
       }
       ++nk;
     }
@@ -233,10 +225,17 @@ __global__ __launch_bounds__(TPB, 1) void k_square_tile_bf16x3(TileArgs a) {
 
 }  // namespace
 
+void launch_pack_bf16x3(Ctx &c, const float *pool, const int32_t *slot, int64_t nblocks, uint16_t *packed) {
+  if (nblocks <= 0) return;
+  k_pack_bf16x3<<<(unsigned)nblocks, TPB, 0, c.stream>>>(pool, slot, nblocks, packed);
+  SP2_LAUNCH_CHECK();
+}
+
 void launch_square_tile_bf16x3(Ctx &c, const TileArgs &a) {
   if (a.ntiles <= 0) return;
   if (a.xprec != P32) fail(SP2_ERR_INVALID_ARG, "BF16x3 square needs an FP32 input pool");
   const bool gen = a.ypool != a.xpool || a.npass != 1 || a.xanti || a.yanti;
+  if (!a.xpack || (gen && !a.ypack)) fail(SP2_ERR_INVALID_ARG, "BF16x3 square needs packed operands");
   const unsigned g = (unsigned)(8 * a.xcd_chunk);
   if (a.oprec == P32) {
     if (gen)

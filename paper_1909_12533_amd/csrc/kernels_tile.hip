@@ -91,7 +91,7 @@ __device__ inline void mma_dispatch(typename MF<T>::acc_t (&acc)[4][4], const T 
 // roles swapped, sign flips of antisymmetric lower blocks); otherwise the
 // square X X with the same code minus that bookkeeping.
 template <typename T, typename TO, bool GEN>
-__global__ __launch_bounds__(TPB, 1) void k_square_tile(TileArgs a) {
+__global__ __launch_bounds__(TPB, sizeof(T) == 4 ? 2 : 1) void k_square_tile(TileArgs a) {
   constexpr int LD = MF<T>::LD;
   __shared__ __align__(16) T As[2][64 * LD];
   __shared__ __align__(16) T Bs[2][64 * LD];

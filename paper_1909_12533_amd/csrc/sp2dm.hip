@@ -233,6 +233,17 @@ DMat borrow_matrix(Ctx &c, const sp2_bsr *M, const char *what) {
 }
 
 // ------------------------------------------------------------------ steps
+// BF16x3 operand images of X (32 KB per pool slot), or an empty buffer for the
+// other arithmetics
+Buf pack_operand(Ctx &c, const DMat &X, int mode) {
+  Buf b;
+  if (mode != M_BF16X3) return b;
+  if (X.pool->prec != P32) fail(SP2_ERR_INVALID_ARG, "BF16x3 operands must hold FP32 values");
+  b = c.alloc((size_t)(X.pool->nslots > 0 ? X.pool->nslots : 1) * BB * 4 * sizeof(uint16_t));
+  launch_pack_bf16x3(c, X.pool->vals.as<float>(), slot_ptr(X.pat), X.pat.nnzb, b.as<uint16_t>());
+  return b;
+}
+
 struct SquareOut {
   DMat next;      // X_{i+1} (or S when fused == false) on the square's pattern
   Buf parts;      // nout x NPART
@@ -272,6 +283,9 @@ SquareOut square_step(Ctx &c, const DMat &X, const Maps &m, int mode, int oprec,
   ta.ybits = ta.bits;
   ta.gpool = ta.xpool;
   ta.gidxmap = ta.idxmap;
+  Buf xpack = pack_operand(c, X, mode);
+  ta.xpack = xpack.p;
+  ta.ypack = xpack.p;
   ta.nbr = X.pat.nbr;
   ta.W = m.W;
   ta.oidx = om.idxmap.as<int32_t>();
@@ -338,6 +352,9 @@ SquareOut pair_product(Ctx &c, const DMat &X, const Maps &mx, const DMat &Y, con
   ta.ypool = Y.pool->vals.p;
   ta.yidxmap = my.idxmap.as<int32_t>();
   ta.ybits = my.bits.as<uint32_t>();
+  Buf xpack = pack_operand(c, X, po.mode), ypack = pack_operand(c, Y, po.mode);
+  ta.xpack = xpack.p;
+  ta.ypack = ypack.p;
   ta.npass = 2;
   ta.neg2 = po.neg2 ? 1 : 0;
   ta.xanti = 0;
@@ -595,11 +612,20 @@ struct CorrStats {
 // formed in FP64 (it is small: the difference of two O(1) products); [D, C]
 // and the derivative steps use the arithmetic the expansion used for each X~_i.
 DMat subspace_correction(Ctx &c, const DMat &F, DMat D, const std::vector<DMat> &seq, const std::vector<int> &p,
-                         const std::vector<double> &alph, double w, const sp2_options &o, int lowmode, double tau_n,
-                         CorrStats &cs) {
+                         const std::vector<double> &alph, const std::vector<double> &e, double w,
+                         const sp2_options &o, int lowmode, double tau_n, CorrStats &cs) {
   const double beta = o.corr_tol > 0.0 ? o.corr_tol : 1e-9;
   const double fl = 2.0 * B * B * B;
-  const int n = (int)seq.size();
+  // Once an iterate is close to a projector P (e_i small), the remaining
+  // derivative steps map dX to P dX (I - P) + (I - P) dX P plus parts inside
+  // the two subspaces, which the purification removes: they change the
+  // correction only at relative order e_i and are skipped.
+  int n = (int)seq.size();
+  for (int i = 1; i < n; ++i)
+    if (e[i] < 1e-3) {
+      n = i;
+      break;
+    }
   auto note = [&](const DMat &M) { cs.max_nnzb = std::max(cs.max_nnzb, M.pat.nnzb); };
   auto drop = [&](DMat &M, const SquareOut &so) {
     note(M);
@@ -879,7 +905,7 @@ int run_density(Ctx &c, const sp2_bsr *Fin, int64_t n_occ, double lmin, double l
   CorrStats cs;
   if (corr) {
     auto t_c = std::chrono::steady_clock::now();
-    X = subspace_correction(c, F, std::move(X), seq, p, alph, w, o, lowmode, taus[n], cs);
+    X = subspace_correction(c, F, std::move(X), seq, p, alph, e, w, o, lowmode, taus[n], cs);
     seq.clear();
     c.sync();
     cs.time_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_c).count();
