@@ -133,6 +133,86 @@ def bsr_diff_frobenius(A, B):
     return float(tot.sqrt())
 
 
+def bsr_inner(A, B):
+    """Frobenius inner product of two symmetric upper-BSR device matrices (whole
+    matrices: off-diagonal blocks count twice)."""
+    import torch
+
+    def keys(M):
+        rows = torch.repeat_interleave(torch.arange(M.nbr, device=M.device), torch.diff(M.row_ptr))
+        return rows, rows * M.nbr + M.col_idx.long()
+
+    ra, ka = keys(A)
+    rb, kb = keys(B)
+    if kb.numel() == 0 or ka.numel() == 0:
+        return 0.0
+    pos = torch.searchsorted(kb, ka).clamp(max=kb.numel() - 1)
+    hit = kb[pos] == ka
+    w = torch.where(ra[hit] == A.col_idx.long()[hit], 1.0, 2.0).double()
+    return float((w * (A.val[hit] * B.val[pos[hit]]).sum(dim=(1, 2))).sum())
+
+
+def adjoint_bench(sp2, F, Fh, no, lmin, lmax, hub, llb, opts, precisions):
+    """Response dD = J dF and gradient of L = tr(W D) through the hand-written
+    adjoint on the workload's F: dF and W random symmetric on F's block pattern
+    (entries N(0, 1e-3) and N(0, 1)), sqrt(n) checkpoints of X~_i.  FP64:
+    central finite differences of the recorded map (h = 1e-5) and the
+    dot-product test; low precision: relative error of J dF and of the gradient
+    against the FP64 ones."""
+    import torch
+
+    from fockgen import random_sym_on_pattern
+
+    dFh = random_sym_on_pattern(Fh, 1e-3, seed=1)
+    Wh = random_sym_on_pattern(Fh, 1.0, seed=2)
+    dF = sp2.BsrMatrix.from_host(dFh, "cuda:0")
+    W = sp2.BsrMatrix.from_host(Wh, "cuda:0")
+    out = {}
+    ref = {}
+    for prec in precisions:
+        mo = dict(precision=prec, switch_tol=1e-3) if prec != "fp64" else {}
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = sp2.density(F, no, lmin, lmax, hub, llb, record_tape=True, **mo, **opts)
+        torch.cuda.synchronize()
+        t_fwd = time.perf_counter() - t0
+        info = r.tape.info()
+        t0 = time.perf_counter()
+        g = r.tape.vjp(W)
+        torch.cuda.synchronize()
+        t_vjp = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        jv = r.tape.jvp(dF)
+        torch.cuda.synchronize()
+        t_jvp = time.perf_counter() - t0
+        rec = {"n_iter": r.n_iter, "forward_s": round(t_fwd, 4), "vjp_s": round(t_vjp, 4), "jvp_s": round(t_jvp, 4),
+               "n_checkpoints": info["n_checkpoints"], "tape_device_bytes": info["device_bytes"],
+               "peak_device_bytes": torch.cuda.max_memory_allocated()}
+        lhs, rhs = bsr_inner(W, jv), bsr_inner(g, dF)
+        rec["dot_test_rel"] = abs(lhs - rhs) / max(abs(lhs), 1e-300)
+        if prec == "fp64":
+            h = 1e-5
+            Fp = sp2.BsrMatrix(F.n, F.row_ptr, F.col_idx, (F.val + h * dF.val).contiguous())
+            Fm = sp2.BsrMatrix(F.n, F.row_ptr, F.col_idx, (F.val - h * dF.val).contiguous())
+            Dp, Dm = r.tape.replay(Fp), r.tape.replay(Fm)
+            if not (torch.equal(Dp.row_ptr, jv.row_ptr) and torch.equal(Dp.col_idx, jv.col_idx)):
+                raise RuntimeError("replay and JVP patterns differ")
+            fd = (Dp.val - Dm.val) / (2 * h)
+            num = bsr_diff_frobenius(sp2.BsrMatrix(F.n, Dp.row_ptr, Dp.col_idx, fd.contiguous()), jv)
+            rec["fd_rel_err_jvp"] = num / math.sqrt(bsr_inner(jv, jv))
+            ref = {"g": g, "jv": jv}
+            del Dp, Dm, Fp, Fm, fd
+        else:
+            rec["grad_rel_err_vs_fp64"] = bsr_diff_frobenius(g, ref["g"]) / math.sqrt(bsr_inner(ref["g"], ref["g"]))
+            rec["jvp_rel_err_vs_fp64"] = bsr_diff_frobenius(jv, ref["jv"]) / math.sqrt(bsr_inner(ref["jv"], ref["jv"]))
+        log(f"adjoint {prec}: {rec}")
+        out[prec] = rec
+        r.tape.free()
+        del r
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -149,6 +229,8 @@ def main():
                     help="Frobenius budget for dropping blocks of the correction's intermediates (library default)")
     ap.add_argument("--compare", default="bf16x3", choices=["none", "fp32", "bf16x3"],
                     help="with --precision fp64: one mixed run (with and without the correction) for speedup / error")
+    ap.add_argument("--adjoint", action="store_true",
+                    help="instead of the expansion benchmark: JVP and VJP of tr(W D) in FP64 and mixed precision")
     ap.add_argument("--switch-tol", type=float, default=None,
                     help="FP64 tail once ||X - X^2||_F < this (default: 0 with the correction, else 1e-3)")
     ap.add_argument("--bounds", default=None,
@@ -194,6 +276,11 @@ def main():
         torch.cuda.synchronize()
         log(f"calibration copy: {nb} bytes read, {nb} bytes written")
         del src, dst
+
+    if args.adjoint:
+        res = adjoint_bench(sp2, F, Fh, no, lmin, lmax, hub, llb, opts, ["fp64", "fp32", "bf16x3"])
+        print(json.dumps({"adjoint": res, "workload": f"lattice {L}^3 x 4, N={info['n']}, tau={tau}"}), flush=True)
+        return
 
     correct = args.correct if args.correct is not None else (0 if prec == "fp64" else 1)
     switch_tol = args.switch_tol if args.switch_tol is not None else (0.0 if correct else 1e-3)

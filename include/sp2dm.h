@@ -112,6 +112,8 @@ typedef struct {
   int32_t corr_purify;  /* FP64 purification squares after each correction round (>= 1; default 2) */
   double corr_tol;      /* Frobenius budget for dropping small blocks of every intermediate of the
                            correction (0 = default 1e-9) */
+  int64_t corr_mem;     /* device bytes for the copies of X~_i kept for the correction; the iterates
+                           beyond that are recomputed (0 = min(30% of the device, 50% of free memory)) */
 } sp2_options;
 
 /* Per-run statistics.  Arrays are HOST arrays owned by the caller, each of
@@ -207,8 +209,11 @@ int sp2_gershgorin(sp2_ctx *ctx, const sp2_bsr *F, double *lmin, double *lmax);
  * Frobenius norm of the dropped part stays within corr_tol.  With
  * switch_tol = 0 the expansion runs in the low precision to its stopping
  * criterion (evaluated on the low-precision e_i) and the purification replaces
- * the FP64 tail.  The X~_i are kept on the device for the correction
- * (stats->seq_bytes). */
+ * the FP64 tail.  Copies of X~_0, X~_1, ... are kept on the device within
+ * corr_mem bytes (stats->seq_bytes); later iterates are recomputed from their
+ * recorded masks and polynomials, bit for bit.  Derivative steps from the
+ * first iterate with e_i < 1e-3 on are skipped: near a projector they only
+ * keep the occupied-virtual part, which the purification leaves in place. */
 
 /* Density matrix by SP2 / SP2ACC (Steps 1-3, Algorithms 1-2).
  *   F         symmetric input in upper BSR (device)

@@ -58,6 +58,7 @@ class sp2_options(C.Structure):
         ("correct", C.c_int32),
         ("corr_purify", C.c_int32),
         ("corr_tol", C.c_double),
+        ("corr_mem", C.c_int64),
     ]
 
 

@@ -611,7 +611,12 @@ struct CorrStats {
 // corr_tol), D <- FP64 purification of D + dD.  The commutator C = [D, F] is
 // formed in FP64 (it is small: the difference of two O(1) products); [D, C]
 // and the derivative steps use the arithmetic the expansion used for each X~_i.
-DMat subspace_correction(Ctx &c, const DMat &F, DMat D, const std::vector<DMat> &seq, const std::vector<int> &p,
+DMat replay_step(Ctx &c, const Tape &t, int i, const DMat &Xprev);
+DMat checkpoint_copy(const Tape &t, int i);
+
+// ct records X~_0 .. X~_{nseq-1} (masks, polynomials, arithmetic) with
+// copies of a prefix of them; the others are recomputed in order.
+DMat subspace_correction(Ctx &c, const DMat &F, DMat D, const Tape &ct, int nseq, const std::vector<int> &p,
                          const std::vector<double> &alph, const std::vector<double> &e, double w,
                          const sp2_options &o, int lowmode, double tau_n, CorrStats &cs) {
   const double beta = o.corr_tol > 0.0 ? o.corr_tol : 1e-9;
@@ -620,7 +625,7 @@ DMat subspace_correction(Ctx &c, const DMat &F, DMat D, const std::vector<DMat> 
   // derivative steps map dX to P dX (I - P) + (I - P) dX P plus parts inside
   // the two subspaces, which the purification removes: they change the
   // correction only at relative order e_i and are skipped.
-  int n = (int)seq.size();
+  int n = nseq;
   for (int i = 1; i < n; ++i)
     if (e[i] < 1e-3) {
       n = i;
@@ -671,8 +676,9 @@ DMat subspace_correction(Ctx &c, const DMat &F, DMat D, const std::vector<DMat> 
       drop(dX, dd);
     }
     // derivative of X_{i+1} = ca I + cb X~_i + cc X~_i^2 along dX~_i
+    DMat Xi;
     for (int i = 0; i < n; ++i) {
-      const DMat &Xi = seq[i];
+      Xi = ct.it[i].ckpt ? checkpoint_copy(ct, i) : replay_step(c, ct, i, Xi);
       const int mi = Xi.pool->prec == P32 ? lowmode : M_F64;
       DMat G = as_prec(c, dX, Xi.pool->prec);
       Maps mX = build_maps(c, Xi.pat, true), mG = build_maps(c, G.pat, true);
@@ -747,6 +753,7 @@ int run_density(Ctx &c, const sp2_bsr *Fin, int64_t n_occ, double lmin, double l
   if (o.correct > 0 && (o.corr_purify < 1 || o.corr_purify > 16))
     fail(SP2_ERR_INVALID_ARG, "corr_purify must be in [1, 16]");
   if (!(o.corr_tol >= 0.0)) fail(SP2_ERR_INVALID_ARG, "corr_tol must be >= 0");
+  if (o.corr_mem < 0) fail(SP2_ERR_INVALID_ARG, "corr_mem must be >= 0");
   const int lowmode = o.precision == SP2_PREC_FP32 ? M_F32 : (o.precision == SP2_PREC_BF16X3 ? M_BF16X3 : M_F64);
   const bool corr = o.correct > 0;
   // with the correction and no switch tolerance the whole expansion stays in
@@ -794,7 +801,21 @@ int run_density(Ctx &c, const sp2_bsr *Fin, int64_t n_occ, double lmin, double l
   int n = -1, stop_reason = 0, status = SP2_OK;
   double alg_flops = 0.0;
   int64_t max_nnzb = 0, seq_bytes = 0;
-  std::vector<DMat> seq;  // X~_0 .. X~_{n-1} for the correction
+  // X~_0 .. X~_{n-1} for the correction: masks and polynomials of every
+  // iteration, copies of the iterates while they fit in a share of the device
+  // memory (the rest are recomputed during the correction)
+  Tape ct;
+  int64_t seq_budget = 0;
+  bool seq_full = false;
+  if (corr) {
+    size_t fr = 0, tot = 0;
+    SP2_HIP(hipMemGetInfo(&fr, &tot));
+    seq_budget = o.corr_mem > 0 ? o.corr_mem : (int64_t)std::min(0.3 * (double)tot, 0.5 * (double)fr);
+    ct.ctx = &c;
+    ct.n = N;
+    ct.lmax = lmax;
+    ct.w = w;
+  }
   for (int i = 0;; ++i) {
     auto t_it = std::chrono::steady_clock::now();
     const int mode = X.pool->prec == P32 ? lowmode : M_F64;
@@ -874,8 +895,24 @@ int run_density(Ctx &c, const sp2_bsr *Fin, int64_t n_occ, double lmin, double l
     p.push_back(pn);
     alph.push_back(an);
     if (corr) {
-      seq.push_back(compact_values(c, X, X.pool->prec));
-      seq_bytes += seq.back().pat.nnzb * (int64_t)BB * (X.pool->prec == P64 ? 8 : 4);
+      ct.it.emplace_back();
+      TapeIter &ti = ct.it.back();
+      ti.mask = clone_pattern(c, X.pat);
+      ti.mask.slot.reset();
+      ti.mode = mode;
+      ti.prec = X.pool->prec;
+      if (i >= 1) {
+        ti.p = p[i];
+        ti.alpha = alph[i];
+        poly_coeffs(p[i], alph[i], ti.ca, ti.cb, ti.cc);
+      }
+      const int64_t bytes = X.pat.nnzb * (int64_t)BB * (X.pool->prec == P64 ? 8 : 4);
+      if (i == 0 || (!seq_full && seq_bytes + bytes <= seq_budget)) {
+        add_checkpoint(c, ct, i, X);
+        seq_bytes += bytes;
+      } else {
+        seq_full = true;
+      }
     }
     DMat Xn = std::move(so.next);
     const int64_t nout = Xn.pat.nnzb;
@@ -905,8 +942,8 @@ int run_density(Ctx &c, const sp2_bsr *Fin, int64_t n_occ, double lmin, double l
   CorrStats cs;
   if (corr) {
     auto t_c = std::chrono::steady_clock::now();
-    X = subspace_correction(c, F, std::move(X), seq, p, alph, e, w, o, lowmode, taus[n], cs);
-    seq.clear();
+    X = subspace_correction(c, F, std::move(X), ct, n, p, alph, e, w, o, lowmode, taus[n], cs);
+    ct.it.clear();
     c.sync();
     cs.time_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_c).count();
     alg_flops += cs.flops;

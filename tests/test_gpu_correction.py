@@ -93,3 +93,20 @@ def test_low_precision_lattice_target(gpu_lib, prec, rounds):
     assert e_ref <= 1e-5
     assert e_st <= e64_st + 1e-6
     assert abs(np.trace(D) - no) <= 1e-6
+
+
+def test_recomputed_iterates_give_identical_result(gpu_lib):
+    """With no room for copies (corr_mem = 1 byte) the correction recomputes
+    X~_1 .. X~_{n-1} from the recorded masks and polynomials: bit-identical D."""
+    sp2 = gpu_lib
+    Fh, info = lattice_fock(6, seed=0)
+    Fd = bsr_to_dense(Fh)
+    no = info["n_occ"]
+    lmin, lmax = O.gershgorin_bounds(Fd)
+    F = sp2.BsrMatrix.from_host(Fh)
+    kw = dict(trunc_norm="frobinf", tau_fixed=1e-5, coarse_bs=128, precision="bf16x3", switch_tol=0.0, correct=1)
+    r1 = sp2.density(F, no, lmin, lmax, -0.37, 0.34, **kw)
+    r2 = sp2.density(F, no, lmin, lmax, -0.37, 0.34, corr_mem=1, **kw)
+    assert r2.correction["seq_bytes"] < r1.correction["seq_bytes"]
+    assert np.array_equal(upper_mask(r1.D), upper_mask(r2.D))
+    assert np.array_equal(to_dense(r1.D), to_dense(r2.D))
