@@ -158,7 +158,8 @@ def adjoint_bench(sp2, F, Fh, no, lmin, lmax, hub, llb, opts, precisions):
     (entries N(0, 1e-3) and N(0, 1)), sqrt(n) checkpoints of X~_i.  FP64:
     central finite differences of the recorded map (h = 1e-5) and the
     dot-product test; low precision: relative error of J dF and of the gradient
-    against the FP64 ones."""
+    against the FP64 ones.  Labels "forward/adjoint" run the adjoint steps of
+    the low-precision iterations in another arithmetic."""
     import torch
 
     from fockgen import random_sym_on_pattern
@@ -169,8 +170,11 @@ def adjoint_bench(sp2, F, Fh, no, lmin, lmax, hub, llb, opts, precisions):
     W = sp2.BsrMatrix.from_host(Wh, "cuda:0")
     out = {}
     ref = {}
-    for prec in precisions:
+    for label in precisions:
+        prec, _, adj = label.partition("/")
         mo = dict(precision=prec, switch_tol=1e-3) if prec != "fp64" else {}
+        if adj:
+            mo["adjoint_precision"] = adj
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         r = sp2.density(F, no, lmin, lmax, hub, llb, record_tape=True, **mo, **opts)
@@ -205,8 +209,8 @@ def adjoint_bench(sp2, F, Fh, no, lmin, lmax, hub, llb, opts, precisions):
         else:
             rec["grad_rel_err_vs_fp64"] = bsr_diff_frobenius(g, ref["g"]) / math.sqrt(bsr_inner(ref["g"], ref["g"]))
             rec["jvp_rel_err_vs_fp64"] = bsr_diff_frobenius(jv, ref["jv"]) / math.sqrt(bsr_inner(ref["jv"], ref["jv"]))
-        log(f"adjoint {prec}: {rec}")
-        out[prec] = rec
+        log(f"adjoint {label}: {rec}")
+        out[label] = rec
         r.tape.free()
         del r
         torch.cuda.empty_cache()
@@ -278,7 +282,7 @@ def main():
         del src, dst
 
     if args.adjoint:
-        res = adjoint_bench(sp2, F, Fh, no, lmin, lmax, hub, llb, opts, ["fp64", "fp32", "bf16x3"])
+        res = adjoint_bench(sp2, F, Fh, no, lmin, lmax, hub, llb, opts, ["fp64", "fp32", "bf16x3", "bf16x3/fp32"])
         print(json.dumps({"adjoint": res, "workload": f"lattice {L}^3 x 4, N={info['n']}, tau={tau}"}), flush=True)
         return
 

@@ -113,7 +113,9 @@ typedef struct {
   double corr_tol;      /* Frobenius budget for dropping small blocks of every intermediate of the
                            correction (0 = default 1e-9) */
   int64_t corr_mem;     /* device bytes for the copies of X~_i kept for the correction; the iterates
-                           beyond that are recomputed (0 = min(30% of the device, 50% of free memory)) */
+                           beyond that are recomputed (0 = min(20% of the device, 35% of free memory)) */
+  int32_t adjoint_precision; /* arithmetic of sp2_vjp / sp2_jvp steps at the iterations the forward ran in
+                           low precision: -1 = the forward's (default), else SP2_PREC_* */
 } sp2_options;
 
 /* Per-run statistics.  Arrays are HOST arrays owned by the caller, each of
@@ -164,7 +166,8 @@ const char *sp2_version(void);
 
 /* Fill *opt with the defaults: SP2ACC, FP64, switch_tol 1e-3, Frob-Inf,
  * n_max_cap 100, coarse_bs 4096, gamma 1e-3, tau_fixed 0, idem_stop 0,
- * no tape, no subspace correction (corr_purify 2, corr_tol 1e-9). */
+ * no tape, no subspace correction (corr_purify 2, corr_tol 1e-9, corr_mem 0),
+ * adjoint_precision -1. */
 void sp2_options_default(sp2_options *opt);
 
 /* Create a context on HIP device `device` issuing all work on `hip_stream`
@@ -238,8 +241,9 @@ int sp2_density(sp2_ctx *ctx, const sp2_bsr *F, int64_t n_occ, double lmin, doub
  * F -> D: Fbar = (dL/dF) for L = tr(W D), W symmetric in upper BSR on any
  * pattern.  X~_i are recomputed from the tape's checkpoints.  Each step
  * Xbar <- cb G + cc (X~ G + G X~) runs in the arithmetic the forward used for
- * that X~_i: FP64, or FP32 values with FP32 / BF16x3 products for the
- * low-precision iterations of a mixed run.  The map excludes the subspace
+ * that X~_i (FP64, or FP32 values with FP32 / BF16x3 products for the
+ * low-precision iterations of a mixed run), or in the one the forward's
+ * options named in adjoint_precision.  The map excludes the subspace
  * correction (sp2_options.correct). */
 int sp2_vjp(sp2_ctx *ctx, const sp2_tape *tape, const sp2_bsr *W, sp2_bsr **Fbar_out);
 

@@ -59,6 +59,7 @@ class sp2_options(C.Structure):
         ("corr_purify", C.c_int32),
         ("corr_tol", C.c_double),
         ("corr_mem", C.c_int64),
+        ("adjoint_precision", C.c_int32),
     ]
 
 

@@ -23,18 +23,18 @@ using namespace dev;
 
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
-// 16-deep k chunk fragments for a wave computing a full 64 x 64 block:
-// four 16-row A tiles and four 16-column B tiles, k index k0 + 4 g + s for
-// MFMA s of the chunk (lane group g = lane / 16).
-template <typename T, bool TA, bool TB> struct Frag4 {
-  T a[4][4], b[4][4];
-  __device__ inline void load(const T *As, const T *Bs, int k0) {
+// 16-deep k chunk fragments for a wave computing MT 16-row tiles (rows
+// r0 + 16 m) of a 64 x 64 block and all four 16-column tiles: k index
+// k0 + 4 g + s for MFMA s of the chunk (lane group g = lane / 16).
+template <typename T, bool TA, bool TB, int MT> struct Frag {
+  T a[MT][4], b[4][4];
+  __device__ inline void load(const T *As, const T *Bs, int k0, int r0) {
     constexpr int LD = MF<T>::LD;
     const int lane = threadIdx.x & 63;
     const int l16 = lane & 15, kb = k0 + 4 * (lane >> 4);
 #pragma unroll
-    for (int m = 0; m < 4; ++m) {
-      const int r = 16 * m + l16;
+    for (int m = 0; m < MT; ++m) {
+      const int r = r0 + 16 * m + l16;
       if (!TA) {
         const T *p = As + r * LD + kb;
 #pragma unroll
@@ -59,57 +59,65 @@ template <typename T, bool TA, bool TB> struct Frag4 {
   }
 };
 
-template <typename T, bool TA, bool TB>
-__device__ inline void mma_full(typename MF<T>::acc_t (&acc)[4][4], const T *As, const T *Bs) {
-  Frag4<T, TA, TB> f;
+template <typename T, bool TA, bool TB, int MT>
+__device__ inline void mma_full(typename MF<T>::acc_t (&acc)[MT][4], const T *As, const T *Bs, int r0) {
+  Frag<T, TA, TB, MT> f;
 #pragma unroll
   for (int kc = 0; kc < 4; ++kc) {
-    f.load(As, Bs, 16 * kc);
+    f.load(As, Bs, 16 * kc, r0);
 #pragma unroll
     for (int s = 0; s < 4; ++s)
 #pragma unroll
-      for (int m = 0; m < 4; ++m)
+      for (int m = 0; m < MT; ++m)
 #pragma unroll
         for (int n = 0; n < 4; ++n) acc[m][n] = MF<T>::op(f.a[m][s], f.b[n][s], acc[m][n]);
   }
 }
 
-template <typename T>
-__device__ inline void mma_dispatch(typename MF<T>::acc_t (&acc)[4][4], const T *As, const T *Bs, bool tA, bool tB) {
+template <typename T, int MT>
+__device__ inline void mma_dispatch(typename MF<T>::acc_t (&acc)[MT][4], const T *As, const T *Bs, bool tA, bool tB,
+                                    int r0) {
   if (!tA && !tB)
-    mma_full<T, false, false>(acc, As, Bs);
+    mma_full<T, false, false, MT>(acc, As, Bs, r0);
   else if (!tA && tB)
-    mma_full<T, false, true>(acc, As, Bs);
+    mma_full<T, false, true, MT>(acc, As, Bs, r0);
   else if (tA && !tB)
-    mma_full<T, true, false>(acc, As, Bs);
+    mma_full<T, true, false, MT>(acc, As, Bs, r0);
   else
-    mma_full<T, true, true>(acc, As, Bs);
+    mma_full<T, true, true, MT>(acc, As, Bs, r0);
 }
-
 
 // GEN: general product (second operand Y, optional second pass with the
 // roles swapped, sign flips of antisymmetric lower blocks); otherwise the
 // square X X with the same code minus that bookkeeping.
-template <typename T, typename TO, bool GEN>
-__global__ __launch_bounds__(TPB, sizeof(T) == 4 ? 2 : 1) void k_square_tile(TileArgs a) {
+// NW = 4: one wave per output block (all 4 x 4 MFMA tiles); NW = 8: two waves
+// per output block, each with the 2 x 4 tiles of rows 32 h .. 32 h + 31, so
+// that every SIMD holds two waves (one multiplies while the other waits on LDS).
+template <typename T, typename TO, bool GEN, int NW>
+__global__ __launch_bounds__(64 * NW, (NW == 4 && sizeof(T) == 4) ? 2 : 1) void k_square_tile(TileArgs a) {
   constexpr int LD = MF<T>::LD;
+  constexpr int NT = 64 * NW;      // threads
+  constexpr int MT = 16 / NW;      // 16-row A tiles per wave
   __shared__ __align__(16) T As[2][64 * LD];
   __shared__ __align__(16) T Bs[2][64 * LD];
+  __shared__ double red[4][4];     // NW = 8: partial sums of the second-half waves
   const int64_t t = xcd_tile(a);
   if (t < 0) return;
   const int nbr = a.nbr, W = a.W;
   const int I0 = 2 * __builtin_amdgcn_readfirstlane(a.tiles[2 * t]);
   const int J0 = 2 * __builtin_amdgcn_readfirstlane(a.tiles[2 * t + 1]);
   const int wave = threadIdx.x >> 6;
-  const int ia = wave >> 1, jb = wave & 1;
+  const int blk = wave & 3, half = wave >> 2;
+  const int row0 = NW == 8 ? 32 * half : 0;
+  const int ia = blk >> 1, jb = blk & 1;
   const int I = I0 + ia, J = J0 + jb;
   const bool has_i1 = I0 + 1 < nbr, has_j1 = J0 + 1 < nbr;
   int32_t pos = -1;
   if (I < nbr && J < nbr && I <= J) pos = __builtin_amdgcn_readfirstlane(a.oidx[(int64_t)I * nbr + J]);
 
-  typename MF<T>::acc_t acc[4][4];
+  typename MF<T>::acc_t acc[MT][4];
 #pragma unroll
-  for (int m = 0; m < 4; ++m)
+  for (int m = 0; m < MT; ++m)
 #pragma unroll
     for (int n = 0; n < 4; ++n) acc[m][n] = typename MF<T>::acc_t{0, 0, 0, 0};
 
@@ -146,7 +154,7 @@ __global__ __launch_bounds__(TPB, sizeof(T) == 4 ? 2 : 1) void k_square_tile(Til
 
   // staged operand blocks A0 = L_{I0,K}, A1 = L_{I0+1,K}, B0 = R_{K,J0}, B1 = R_{K,J0+1}
   // with (L, R) = (X, Y) in the first pass and (Y, X) in the second
-  constexpr int NCH = Stage<T>::NCH;
+  constexpr int NCH = BB / Stage<T>::EPC / NT;  // 16-byte chunks per thread and block
   constexpr int QB = BB * (int)sizeof(T) / 16;  // 16-byte chunks per block
   constexpr uint32_t SGN = 0x80000000u;
   const u32x4 *xq = reinterpret_cast<const u32x4 *>(a.xpool);
@@ -159,7 +167,7 @@ __global__ __launch_bounds__(TPB, sizeof(T) == 4 ? 2 : 1) void k_square_tile(Til
   do {                                                                            \
     if ((SL) >= 0) {                                                              \
       const u32x4 *src_ = (Q) + (int64_t)(SL) * QB + threadIdx.x;                 \
-      _Pragma("unroll") for (int j = 0; j < NCH; ++j) R[j] = src_[j * TPB];       \
+      _Pragma("unroll") for (int j = 0; j < NCH; ++j) R[j] = src_[j * NT];        \
     } else {                                                                      \
       _Pragma("unroll") for (int j = 0; j < NCH; ++j) R[j] = u32x4{0u, 0u, 0u, 0u}; \
     }                                                                             \
@@ -201,7 +209,7 @@ __global__ __launch_bounds__(TPB, sizeof(T) == 4 ? 2 : 1) void k_square_tile(Til
       const u32x4 m2 = u32x4{lo2, g2, lo2, g2}, m3 = u32x4{lo3, g3, lo3, g3};
 #pragma unroll
       for (int j = 0; j < NCH; ++j) {
-        const int e = (j * TPB + (int)threadIdx.x) * Stage<T>::EPC;
+        const int e = (j * NT + (int)threadIdx.x) * Stage<T>::EPC;
         const int o = (e >> 6) * LD + (e & 63);
         *reinterpret_cast<u32x4 *>(&As[0][o]) = r0[j] ^ m0;
         *reinterpret_cast<u32x4 *>(&As[1][o]) = r1[j] ^ m1;
@@ -211,7 +219,7 @@ __global__ __launch_bounds__(TPB, sizeof(T) == 4 ? 2 : 1) void k_square_tile(Til
     } else {
 #pragma unroll
       for (int j = 0; j < NCH; ++j) {
-        const int e = (j * TPB + (int)threadIdx.x) * Stage<T>::EPC;
+        const int e = (j * NT + (int)threadIdx.x) * Stage<T>::EPC;
         const int o = (e >> 6) * LD + (e & 63);
         *reinterpret_cast<u32x4 *>(&As[0][o]) = r0[j];
         *reinterpret_cast<u32x4 *>(&As[1][o]) = r1[j];
@@ -224,16 +232,39 @@ __global__ __launch_bounds__(TPB, sizeof(T) == 4 ? 2 : 1) void k_square_tile(Til
     if (Kn >= 0) SP2_ISSUE(Kn, kpass);  // next K's blocks in flight during the MFMAs
     const int32_t sa = ia ? c1 : c0, sb = jb ? c3 : c2;
     if (pos >= 0 && sa >= 0 && sb >= 0) {
-      mma_dispatch<T>(acc, ia ? As[1] : As[0], jb ? Bs[1] : Bs[0], I > K, K > J);
+      mma_dispatch<T, MT>(acc, ia ? As[1] : As[0], jb ? Bs[1] : Bs[0], I > K, K > J, row0);
       ++nk;
     }
     K = Kn;
   }
 #undef SP2_ISSUE
 #undef SP2_LOAD_BLOCK
-  if (pos < 0) return;
-
-  square_epilogue<T, TO>(acc, a, I, J, pos, nk, [](int g, int q) { return MF<T>::row(g, q); });
+  const auto rowf = [](int g, int q) { return MF<T>::row(g, q); };
+  if constexpr (NW == 4) {
+    if (pos < 0) return;
+    square_epilogue<T, TO>(acc, a, I, J, pos, nk, rowf);
+  } else {
+  // two waves per block: the second half's partial sums are added (in a fixed
+  // order) by the first half's wave
+  EpiSums ps{};
+  if (pos >= 0) ps = epilogue_rows<T, TO, MT>(acc, a, I, J, pos, row0, rowf);
+  const int lane = threadIdx.x & 63;
+  if (half == 1 && lane == 0) {
+    red[blk][0] = ps.e2;
+    red[blk][1] = ps.tx;
+    red[blk][2] = ps.ts;
+    red[blk][3] = ps.nr;
+  }
+  __syncthreads();
+  if (half == 0 && lane == 0 && pos >= 0) {
+    double *p = a.parts + (int64_t)pos * NPART;
+    p[0] = ps.e2 + red[blk][0];
+    p[1] = ps.tx + red[blk][1];
+    p[2] = ps.ts + red[blk][2];
+    p[3] = ps.nr + red[blk][3];
+    p[4] = (double)nk;
+  }
+  }
 }
 
 // Tile order: super-tiles of ST x ST tiles (2 ST x 2 ST output blocks) in
@@ -307,21 +338,21 @@ void launch_square_tile(Ctx &c, int mode, const TileArgs &a) {
   if (mode == M_F64) {
     if (a.xprec != P64 || a.oprec != P64) fail(SP2_ERR_INVALID_ARG, "FP64 square needs FP64 pools");
     if (gen)
-      k_square_tile<double, double, true><<<g, TPB, 0, c.stream>>>(a);
+      k_square_tile<double, double, true, 8><<<g, 512, 0, c.stream>>>(a);
     else
-      k_square_tile<double, double, false><<<g, TPB, 0, c.stream>>>(a);
+      k_square_tile<double, double, false, 8><<<g, 512, 0, c.stream>>>(a);
   } else if (mode == M_F32) {
     if (a.xprec != P32) fail(SP2_ERR_INVALID_ARG, "FP32 square needs an FP32 input pool");
     if (a.oprec == P32) {
       if (gen)
-        k_square_tile<float, float, true><<<g, TPB, 0, c.stream>>>(a);
+        k_square_tile<float, float, true, 4><<<g, TPB, 0, c.stream>>>(a);
       else
-        k_square_tile<float, float, false><<<g, TPB, 0, c.stream>>>(a);
+        k_square_tile<float, float, false, 4><<<g, TPB, 0, c.stream>>>(a);
     } else {
       if (gen)
-        k_square_tile<float, double, true><<<g, TPB, 0, c.stream>>>(a);
+        k_square_tile<float, double, true, 4><<<g, TPB, 0, c.stream>>>(a);
       else
-        k_square_tile<float, double, false><<<g, TPB, 0, c.stream>>>(a);
+        k_square_tile<float, double, false, 4><<<g, TPB, 0, c.stream>>>(a);
     }
   } else if (mode == M_BF16X3) {
     launch_square_tile_bf16x3(c, a);

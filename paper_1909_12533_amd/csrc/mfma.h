@@ -63,15 +63,19 @@ __device__ inline double wave_sum(double v) {
   return v;
 }
 
-// Epilogue for the 64 x 64 output block (I, J) held by one wave in 4 x 4 MFMA
-// 16 x 16 accumulator tiles S: out = ca I + cb G + cc S is written at pattern
-// position pos, and the block's partial sums (||G - S||^2 weighted by 2 off the
-// diagonal, tr G, tr S, ||out||^2, #K) go to parts.  In the square G = X, so
+// Epilogue for the rows r0 + 16 m + rowf(g, v) (m < MT) of the 64 x 64 output
+// block (I, J), held by one wave in MT x 4 MFMA 16 x 16 accumulator tiles S:
+// out = ca I + cb G + cc S is written at pattern position pos, and the
+// wave's partial sums (||G - S||^2 weighted by 2 off the diagonal, tr G, tr S,
+// ||out||^2) are returned, reduced over the wave.  In the square G = X, so
 // these are e^2, tr X~ and tr X~^2.
-// rowf(g, v) is the tile row of accumulator element v of lane group g.
-template <typename T, typename TO, typename ACC, typename RowF>
-__device__ inline void square_epilogue(const ACC (&acc)[4][4], const TileArgs &a, int I, int J, int pos, int nk,
-                                       RowF rowf) {
+struct EpiSums {
+  double e2, tx, ts, nr;
+};
+
+template <typename T, typename TO, int MT, typename ACC, typename RowF>
+__device__ inline EpiSums epilogue_rows(const ACC (&acc)[MT][4], const TileArgs &a, int I, int J, int pos, int r0,
+                                        RowF rowf) {
   const int lane = threadIdx.x & 63;
   const int l16 = lane & 15, g = lane >> 4;
   const int32_t sx = a.gpool ? a.gidxmap[(int64_t)I * a.nbr + J] : -1;
@@ -79,12 +83,12 @@ __device__ inline void square_epilogue(const ACC (&acc)[4][4], const TileArgs &a
   TO *ob = static_cast<TO *>(a.opool) + (int64_t)pos * BB;
   double e2 = 0.0, tx = 0.0, ts = 0.0, nr = 0.0;
 #pragma unroll
-  for (int m = 0; m < 4; ++m)
+  for (int m = 0; m < MT; ++m)
 #pragma unroll
     for (int n = 0; n < 4; ++n)
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int r = 16 * m + rowf(g, q);
+        const int r = r0 + 16 * m + rowf(g, q);
         const int c = 16 * n + l16;
         const double s = (double)acc[m][n][q];
         const double x = xb ? (double)xb[r * 64 + c] : 0.0;
@@ -102,16 +106,26 @@ __device__ inline void square_epilogue(const ACC (&acc)[4][4], const TileArgs &a
           ts += s;
         }
       }
-  e2 = wave_sum(e2);
-  tx = wave_sum(tx);
-  ts = wave_sum(ts);
-  nr = wave_sum(nr);
-  if (lane == 0) {
+  EpiSums ps;
+  ps.e2 = wave_sum((I == J) ? e2 : 2.0 * e2);
+  ps.tx = wave_sum(tx);
+  ps.ts = wave_sum(ts);
+  ps.nr = wave_sum(nr);
+  return ps;
+}
+
+// the whole block in one wave (4 x 4 tiles): write the block's parts {e^2, tr G,
+// tr S, ||out||^2, #K}
+template <typename T, typename TO, typename ACC, typename RowF>
+__device__ inline void square_epilogue(const ACC (&acc)[4][4], const TileArgs &a, int I, int J, int pos, int nk,
+                                       RowF rowf) {
+  const EpiSums ps = epilogue_rows<T, TO, 4>(acc, a, I, J, pos, 0, rowf);
+  if ((threadIdx.x & 63) == 0) {
     double *p = a.parts + (int64_t)pos * NPART;
-    p[0] = (I == J) ? e2 : 2.0 * e2;
-    p[1] = tx;
-    p[2] = ts;
-    p[3] = nr;
+    p[0] = ps.e2;
+    p[1] = ps.tx;
+    p[2] = ps.ts;
+    p[3] = ps.nr;
     p[4] = (double)nk;
   }
 }

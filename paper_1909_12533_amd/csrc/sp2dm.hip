@@ -578,7 +578,9 @@ struct Tape {
   double lmax = 0.0, w = 1.0;
   int n_iter = 0, n_ckpt = 0;
   int64_t bytes = 0;
+  int adj_mode = -1;  // arithmetic of adjoint steps at low-precision iterations (-1: as recorded)
   std::vector<TapeIter> it;
+  int step_mode(int i) const { return (adj_mode >= 0 && it[i].mode != M_F64) ? adj_mode : it[i].mode; }
 };
 
 }  // namespace sp2
@@ -645,10 +647,10 @@ DMat subspace_correction(Ctx &c, const DMat &F, DMat D, const Tape &ct, int nseq
       D = compact_values(c, D, D.pool->prec);
       sym_diag(c, D, 1.0);
     }
-    DMat D64 = as_prec(c, D, P64);
     // C = D F - F D, antisymmetric, FP64
     DMat C;
     {
+      DMat D64 = as_prec(c, D, P64);
       Maps mD = build_maps(c, D64.pat, true), mF = build_maps(c, F.pat, true);
       PairOpt pc;
       pc.neg2 = true;
@@ -662,6 +664,7 @@ DMat subspace_correction(Ctx &c, const DMat &F, DMat D, const Tape &ct, int nseq
     DMat dX;
     {
       DMat Dl = as_prec(c, D, lp), Cl = as_prec(c, C, lp);
+      C = DMat();  // only its low-precision copy is needed from here on
       Maps mD = build_maps(c, Dl.pat, true), mC = build_maps(c, Cl.pat, true);
       PairOpt pd;
       pd.neg2 = true;
@@ -697,7 +700,7 @@ DMat subspace_correction(Ctx &c, const DMat &F, DMat D, const Tape &ct, int nseq
       drop(dX, jo);
     }
     cs.step_norm = frob_norm(c, dX);
-    DMat P = add_union(c, D64, 1.0, dX, 1.0);
+    DMat P = add_union(c, D, 1.0, dX, 1.0);
     note(P);
     for (int k = 0; k < o.corr_purify; ++k) {
       double ca, cb, cc;
@@ -754,6 +757,7 @@ int run_density(Ctx &c, const sp2_bsr *Fin, int64_t n_occ, double lmin, double l
     fail(SP2_ERR_INVALID_ARG, "corr_purify must be in [1, 16]");
   if (!(o.corr_tol >= 0.0)) fail(SP2_ERR_INVALID_ARG, "corr_tol must be >= 0");
   if (o.corr_mem < 0) fail(SP2_ERR_INVALID_ARG, "corr_mem must be >= 0");
+  if (o.adjoint_precision < -1 || o.adjoint_precision > 2) fail(SP2_ERR_INVALID_ARG, "unknown adjoint_precision");
   const int lowmode = o.precision == SP2_PREC_FP32 ? M_F32 : (o.precision == SP2_PREC_BF16X3 ? M_BF16X3 : M_F64);
   const bool corr = o.correct > 0;
   // with the correction and no switch tolerance the whole expansion stays in
@@ -779,6 +783,9 @@ int run_density(Ctx &c, const sp2_bsr *Fin, int64_t n_occ, double lmin, double l
     tape->n_occ = n_occ;
     tape->lmax = lmax;
     tape->w = w;
+    tape->adj_mode = o.adjoint_precision < 0 ? -1
+                     : (o.adjoint_precision == SP2_PREC_FP64 ? M_F64
+                        : (o.adjoint_precision == SP2_PREC_FP32 ? M_F32 : M_BF16X3));
     const int nck = o.n_checkpoints > 0 ? o.n_checkpoints : (int)std::ceil(std::sqrt((double)(n_max + 1)));
     ck_every = std::max(1, (int)std::ceil((double)(n_max + 1) / (double)nck));
   }
@@ -810,7 +817,7 @@ int run_density(Ctx &c, const sp2_bsr *Fin, int64_t n_occ, double lmin, double l
   if (corr) {
     size_t fr = 0, tot = 0;
     SP2_HIP(hipMemGetInfo(&fr, &tot));
-    seq_budget = o.corr_mem > 0 ? o.corr_mem : (int64_t)std::min(0.3 * (double)tot, 0.5 * (double)fr);
+    seq_budget = o.corr_mem > 0 ? o.corr_mem : (int64_t)std::min(0.2 * (double)tot, 0.35 * (double)fr);
     ct.ctx = &c;
     ct.n = N;
     ct.lmax = lmax;
@@ -1093,7 +1100,7 @@ sp2_bsr *run_vjp(Ctx &c, const Tape &t, const sp2_bsr *Win) {
       seg_hi = i - 1;
     }
     const TapeIter &ti = t.it[i];
-    Xbar = anticommutator(c, Xbar, seg[(i - 1) - seg_lo], t.it[i - 1].mask, ti.cb, ti.cc, t.it[i - 1].mode);
+    Xbar = anticommutator(c, Xbar, seg[(i - 1) - seg_lo], t.it[i - 1].mask, ti.cb, ti.cc, t.step_mode(i - 1));
     if (i - 1 < seg_hi) seg.resize((i - 1) - seg_lo + 1);  // drop X~ no longer needed
     seg_hi = i - 1;
   }
@@ -1113,7 +1120,7 @@ sp2_bsr *run_jvp(Ctx &c, const Tape &t, const sp2_bsr *dFin) {
   DMat X = checkpoint_copy(t, 0);
   for (int i = 1; i <= t.n_iter; ++i) {
     const TapeIter &ti = t.it[i];
-    DMat nd = anticommutator(c, dX, X, ti.mask, ti.cb, ti.cc, t.it[i - 1].mode);
+    DMat nd = anticommutator(c, dX, X, ti.mask, ti.cb, ti.cc, t.step_mode(i - 1));
     dX = std::move(nd);
     if (i < t.n_iter) X = replay_step(c, t, i, X);
   }
@@ -1177,6 +1184,8 @@ void sp2_options_default(sp2_options *o) {
   o->correct = 0;
   o->corr_purify = 2;
   o->corr_tol = 1e-9;
+  o->corr_mem = 0;
+  o->adjoint_precision = -1;
 }
 
 int sp2_create(sp2_ctx **ctx, int device, void *hip_stream) {

@@ -110,6 +110,13 @@ class Context:
                 try:
                     return torch.cuda.caching_allocator_alloc(int(nbytes), device=dev, stream=stream)
                 except Exception:
+                    pass
+                # blocks cached by PyTorch but unused (possibly fragmented): release, retry once
+                try:
+                    torch.cuda.synchronize(dev)
+                    torch.cuda.empty_cache()
+                    return torch.cuda.caching_allocator_alloc(int(nbytes), device=dev, stream=stream)
+                except Exception:
                     return None
 
             def _free(ptr, user):
@@ -183,7 +190,7 @@ def options(**kw):
     o = L.sp2_options()
     L.load().sp2_options_default(C.byref(o))
     for k, v in kw.items():
-        if k == "precision":
+        if k in ("precision", "adjoint_precision"):
             v = _PREC[v] if isinstance(v, str) else int(v)
         elif k == "trunc_norm":
             v = _NORM[v] if isinstance(v, str) else int(v)
