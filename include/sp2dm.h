@@ -113,7 +113,7 @@ typedef struct {
   double corr_tol;      /* Frobenius budget for dropping small blocks of every intermediate of the
                            correction (0 = default 1e-9) */
   int64_t corr_mem;     /* device bytes for the copies of X~_i kept for the correction; the iterates
-                           beyond that are recomputed (0 = min(20% of the device, 35% of free memory)) */
+                           beyond that are recomputed (0 = min(15% of the device, 25% of free memory)) */
   int32_t adjoint_precision; /* arithmetic of sp2_vjp / sp2_jvp steps at the iterations the forward ran in
                            low precision: -1 = the forward's (default), else SP2_PREC_* */
 } sp2_options;
@@ -156,6 +156,7 @@ typedef struct {
   double corr_e_last;      /* ||P - P^2||_F of the input P of the last purification square */
   int64_t corr_max_nnzb;   /* largest pattern among the correction's intermediates */
   int64_t seq_bytes;       /* device bytes of the stored X~_i sequence the correction replays */
+  int64_t device_peak_bytes; /* largest device memory the library held at once during the call */
 } sp2_stats;
 
 typedef void *(*sp2_alloc_fn)(size_t bytes, void *user);
@@ -198,8 +199,9 @@ int sp2_gershgorin(sp2_ctx *ctx, const sp2_bsr *F, double *lmin, double *lmax);
  * subspace is not recovered); an FP64 tail restores idempotency and trace but
  * not the subspace.  After the expansion, each round takes the current
  * D (a near-projector) and
- *   Delta = [D, [D, F]] = D F (I - D) + (I - D) F D          (FP64 commutator
- *           C = [D, F] first: C is small, so [D, C] may use the low precision)
+ *   Delta = [D, [D, F]] = D F (I - D) + (I - D) F D          (C = [D, F] is
+ *           accumulated in FP64; it is small, so it is stored and [D, C] is
+ *           formed in the low precision)
  *   dD    = J Delta, J the derivative of the expansion's map F -> D
  *           (dX~_0 = -Delta / (lmax - lmin), dX~_i = b_i dX~_{i-1}
  *           + c_i (X~_{i-1} dX~_{i-1} + dX~_{i-1} X~_{i-1}) along the stored

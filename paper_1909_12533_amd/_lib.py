@@ -104,6 +104,7 @@ class sp2_stats(C.Structure):
         ("corr_e_last", C.c_double),
         ("corr_max_nnzb", C.c_int64),
         ("seq_bytes", C.c_int64),
+        ("device_peak_bytes", C.c_int64),
     ]
 
 

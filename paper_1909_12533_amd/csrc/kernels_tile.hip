@@ -336,11 +336,15 @@ void launch_square_tile(Ctx &c, int mode, const TileArgs &a) {
     fail(SP2_ERR_INVALID_ARG, "tiled product: incomplete second operand");
   const unsigned g = (unsigned)(8 * a.xcd_chunk);
   if (mode == M_F64) {
-    if (a.xprec != P64 || a.oprec != P64) fail(SP2_ERR_INVALID_ARG, "FP64 square needs FP64 pools");
-    if (gen)
+    if (a.xprec != P64) fail(SP2_ERR_INVALID_ARG, "FP64 square needs FP64 input pools");
+    if (a.oprec == P32) {  // FP64 arithmetic, result rounded to FP32 (the correction's commutator)
+      if (!gen) fail(SP2_ERR_INVALID_ARG, "FP64 square with FP32 output is for products only");
+      k_square_tile<double, float, true, 8><<<g, 512, 0, c.stream>>>(a);
+    } else if (gen) {
       k_square_tile<double, double, true, 8><<<g, 512, 0, c.stream>>>(a);
-    else
+    } else {
       k_square_tile<double, double, false, 8><<<g, 512, 0, c.stream>>>(a);
+    }
   } else if (mode == M_F32) {
     if (a.xprec != P32) fail(SP2_ERR_INVALID_ARG, "FP32 square needs an FP32 input pool");
     if (a.oprec == P32) {

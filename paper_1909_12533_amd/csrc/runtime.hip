@@ -56,7 +56,7 @@ Buf Ctx::alloc(size_t bytes) {
   bytes = round_bytes(bytes);
   Buf b;
   auto it = cache.lower_bound(bytes);
-  if (it != cache.end() && it->first <= 2 * bytes) {
+  if (it != cache.end() && it->first <= bytes + bytes / 4) {
     b.p = it->second;
     b.bytes = it->first;
     cached_bytes -= it->first;
@@ -68,7 +68,13 @@ Buf Ctx::alloc(size_t bytes) {
       trim();
       p = raw_alloc(bytes);
     }
-    if (!p) fail(SP2_ERR_OOM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+    if (!p) {
+      size_t fr = 0, tot = 0;
+      (void)hipMemGetInfo(&fr, &tot);
+      fail(SP2_ERR_OOM, "device allocation of " + std::to_string(bytes) + " bytes failed (library live " +
+                            std::to_string(live_bytes) + " bytes, device free " + std::to_string(fr) + " of " +
+                            std::to_string(tot) + ")");
+    }
     b.p = p;
     b.bytes = bytes;
   }
@@ -78,8 +84,16 @@ Buf Ctx::alloc(size_t bytes) {
   return b;
 }
 
+// Buffers up to 64 MB are kept for reuse (the many small pattern, map and
+// reduction arrays of every iteration); larger ones go straight back to the
+// allocator, which can split and merge them (matrix pools are tens of GB at
+// the largest workloads, and holding them here would strand that memory).
 void Ctx::release(void *p, size_t bytes) {
   live_bytes -= bytes;
+  if (bytes > ((size_t)64 << 20)) {
+    raw_free(p);
+    return;
+  }
   cache.emplace(bytes, p);
   cached_bytes += bytes;
 }

@@ -328,6 +328,7 @@ struct PairOpt {
 // adjacency lists when the output pattern is the product's own.
 SquareOut pair_product(Ctx &c, const DMat &X, const Maps &mx, const DMat &Y, const Maps &my, const PairOpt &po) {
   const int need = po.mode == M_F64 ? P64 : P32;
+  if (po.mode == M_F64 && po.oprec == P32 && po.G) fail(SP2_ERR_INVALID_ARG, "pair product: FP32 output takes no G");
   if (X.pool->prec != need || Y.pool->prec != need || (po.G && po.G->pool->prec != need))
     fail(SP2_ERR_INVALID_ARG, "pair product: operand precision does not match the arithmetic");
   if (X.pat.nbr != Y.pat.nbr) fail(SP2_ERR_INVALID_ARG, "pair product: operand sizes differ");
@@ -647,13 +648,15 @@ DMat subspace_correction(Ctx &c, const DMat &F, DMat D, const Tape &ct, int nseq
       D = compact_values(c, D, D.pool->prec);
       sym_diag(c, D, 1.0);
     }
-    // C = D F - F D, antisymmetric, FP64
+    // C = D F - F D, antisymmetric, in FP64 arithmetic (stored in the low
+    // precision: the cancellation happens in the accumulators)
     DMat C;
     {
       DMat D64 = as_prec(c, D, P64);
       Maps mD = build_maps(c, D64.pat, true), mF = build_maps(c, F.pat, true);
       PairOpt pc;
       pc.neg2 = true;
+      pc.oprec = lp;
       SquareOut co = pair_product(c, D64, mD, F, mF, pc);
       cs.flops += co.sums[4] * fl;
       C = std::move(co.next);
@@ -664,7 +667,7 @@ DMat subspace_correction(Ctx &c, const DMat &F, DMat D, const Tape &ct, int nseq
     DMat dX;
     {
       DMat Dl = as_prec(c, D, lp), Cl = as_prec(c, C, lp);
-      C = DMat();  // only its low-precision copy is needed from here on
+      C = DMat();
       Maps mD = build_maps(c, Dl.pat, true), mC = build_maps(c, Cl.pat, true);
       PairOpt pd;
       pd.neg2 = true;
@@ -765,6 +768,7 @@ int run_density(Ctx &c, const sp2_bsr *Fin, int64_t n_occ, double lmin, double l
   const bool low_to_end = corr && !(o.switch_tol > 0.0);
 
   auto t_start = std::chrono::steady_clock::now();
+  c.peak_bytes = c.live_bytes;
   DMat F = borrow_matrix(c, Fin, "F");
   check_finite(c, Fin->val, Fin->nnzb * (int64_t)BB, "F");
 
@@ -817,7 +821,7 @@ int run_density(Ctx &c, const sp2_bsr *Fin, int64_t n_occ, double lmin, double l
   if (corr) {
     size_t fr = 0, tot = 0;
     SP2_HIP(hipMemGetInfo(&fr, &tot));
-    seq_budget = o.corr_mem > 0 ? o.corr_mem : (int64_t)std::min(0.2 * (double)tot, 0.35 * (double)fr);
+    seq_budget = o.corr_mem > 0 ? o.corr_mem : (int64_t)std::min(0.15 * (double)tot, 0.25 * (double)fr);
     ct.ctx = &c;
     ct.n = N;
     ct.lmax = lmax;
@@ -1005,6 +1009,7 @@ int run_density(Ctx &c, const sp2_bsr *Fin, int64_t n_occ, double lmin, double l
     st->corr_e_last = cs.e_last;
     st->corr_max_nnzb = cs.max_nnzb;
     st->seq_bytes = seq_bytes;
+    st->device_peak_bytes = (int64_t)c.peak_bytes;
     for (int i = 0; i <= n; ++i) {
       if (st->square_time_s) st->square_time_s[i] = ksq[i];
       if (st->e) st->e[i] = e[i];

@@ -105,13 +105,32 @@ class Context:
         self._cb = None
         if torch_allocator:
             dev, stream = self.device.index, self.stream
+            hip = _hip_runtime()
+            big = set()  # pointers from hipMalloc
+
+            def _hip_malloc(nbytes):
+                p = C.c_void_p()
+                hip.hipSetDevice(dev)
+                if hip.hipMalloc(C.byref(p), C.c_size_t(int(nbytes))) != 0 or not p.value:
+                    return None
+                big.add(p.value)
+                return p.value
 
             def _alloc(nbytes, user):
+                # matrix pools (hundreds of MB to tens of GB) bypass the caching
+                # allocator, whose split segments could not serve the next large
+                # request; small buffers reuse PyTorch's cache
+                if nbytes >= _BIG_ALLOC:
+                    p = _hip_malloc(nbytes)
+                    if p is None:
+                        torch.cuda.synchronize(dev)
+                        torch.cuda.empty_cache()
+                        p = _hip_malloc(nbytes)
+                    return p
                 try:
                     return torch.cuda.caching_allocator_alloc(int(nbytes), device=dev, stream=stream)
                 except Exception:
                     pass
-                # blocks cached by PyTorch but unused (possibly fragmented): release, retry once
                 try:
                     torch.cuda.synchronize(dev)
                     torch.cuda.empty_cache()
@@ -120,7 +139,11 @@ class Context:
                     return None
 
             def _free(ptr, user):
-                torch.cuda.caching_allocator_delete(ptr)
+                if ptr in big:
+                    big.discard(ptr)
+                    hip.hipFree(C.c_void_p(ptr))  # waits for the device work that may use it
+                else:
+                    torch.cuda.caching_allocator_delete(ptr)
 
             self._cb = (L.ALLOC_FN(_alloc), L.FREE_FN(_free))
             self._check(self.lib.sp2_set_allocator(self.h, self._cb[0], self._cb[1], None))
@@ -162,6 +185,32 @@ class Context:
 
 
 _CTX = {}
+
+_BIG_ALLOC = 256 << 20
+_HIP = None
+
+
+def _hip_runtime():
+    """The HIP runtime PyTorch already loaded (hipMalloc / hipFree for large
+    library buffers)."""
+    global _HIP
+    if _HIP is None:
+        for name in ("libamdhip64.so", "libamdhip64.so.7", "/opt/rocm/lib/libamdhip64.so"):
+            try:
+                lib = C.CDLL(name)
+                break
+            except OSError:
+                lib = None
+        if lib is None:
+            raise RuntimeError("HIP runtime library not found")
+        lib.hipMalloc.restype = C.c_int
+        lib.hipMalloc.argtypes = [C.POINTER(C.c_void_p), C.c_size_t]
+        lib.hipFree.restype = C.c_int
+        lib.hipFree.argtypes = [C.c_void_p]
+        lib.hipSetDevice.restype = C.c_int
+        lib.hipSetDevice.argtypes = [C.c_int]
+        _HIP = lib
+    return _HIP
 
 
 def context(device=None) -> Context:
@@ -309,7 +358,8 @@ def density(F: BsrMatrix, n_occ: int, lmin: float, lmax: float, homo_ub=None, lu
                          square_time_s=float(st.square_time_total_s),
                          correction={k: getattr(st, k) for k in ("corr_rounds", "corr_time_s", "corr_flops",
                                                                  "corr_delta_norm", "corr_step_norm", "corr_e_last",
-                                                                 "corr_max_nnzb", "seq_bytes")},
+                                                                 "corr_max_nnzb", "seq_bytes",
+                                                                 "device_peak_bytes")},
                          iters=iters, tape=Tape(ctx, tape_h) if o.record_tape else None)
 
 
