@@ -191,7 +191,7 @@ def adjoint_bench(sp2, F, Fh, no, lmin, lmax, hub, llb, opts, precisions):
         t_jvp = time.perf_counter() - t0
         rec = {"n_iter": r.n_iter, "forward_s": round(t_fwd, 4), "vjp_s": round(t_vjp, 4), "jvp_s": round(t_jvp, 4),
                "n_checkpoints": info["n_checkpoints"], "tape_device_bytes": info["device_bytes"],
-               "peak_device_bytes": torch.cuda.max_memory_allocated()}
+               "forward_device_peak_bytes": r.correction["device_peak_bytes"]}
         lhs, rhs = bsr_inner(W, jv), bsr_inner(g, dF)
         rec["dot_test_rel"] = abs(lhs - rhs) / max(abs(lhs), 1e-300)
         if prec == "fp64":
@@ -206,7 +206,7 @@ def adjoint_bench(sp2, F, Fh, no, lmin, lmax, hub, llb, opts, precisions):
             rec["fd_rel_err_jvp"] = num / math.sqrt(bsr_inner(jv, jv))
             ref = {"g": g, "jv": jv}
             del Dp, Dm, Fp, Fm, fd
-        else:
+        elif ref:
             rec["grad_rel_err_vs_fp64"] = bsr_diff_frobenius(g, ref["g"]) / math.sqrt(bsr_inner(ref["g"], ref["g"]))
             rec["jvp_rel_err_vs_fp64"] = bsr_diff_frobenius(jv, ref["jv"]) / math.sqrt(bsr_inner(ref["jv"], ref["jv"]))
         log(f"adjoint {label}: {rec}")
@@ -231,10 +231,14 @@ def main():
                     help="subspace-correction rounds (default: 0 for fp64, 1 for fp32 / bf16x3)")
     ap.add_argument("--corr-tol", type=float, default=None,
                     help="Frobenius budget for dropping blocks of the correction's intermediates (library default)")
+    ap.add_argument("--no-reference", action="store_true",
+                    help="with a low --precision: skip the FP64 reference run (largest workloads)")
     ap.add_argument("--compare", default="bf16x3", choices=["none", "fp32", "bf16x3"],
                     help="with --precision fp64: one mixed run (with and without the correction) for speedup / error")
     ap.add_argument("--adjoint", action="store_true",
                     help="instead of the expansion benchmark: JVP and VJP of tr(W D) in FP64 and mixed precision")
+    ap.add_argument("--adjoint-runs", default="fp64,fp32,bf16x3,bf16x3/fp32",
+                    help="forward[/adjoint] arithmetics of the adjoint benchmark (errors need fp64 first)")
     ap.add_argument("--switch-tol", type=float, default=None,
                     help="FP64 tail once ||X - X^2||_F < this (default: 0 with the correction, else 1e-3)")
     ap.add_argument("--bounds", default=None,
@@ -282,7 +286,7 @@ def main():
         del src, dst
 
     if args.adjoint:
-        res = adjoint_bench(sp2, F, Fh, no, lmin, lmax, hub, llb, opts, ["fp64", "fp32", "bf16x3", "bf16x3/fp32"])
+        res = adjoint_bench(sp2, F, Fh, no, lmin, lmax, hub, llb, opts, args.adjoint_runs.split(","))
         print(json.dumps({"adjoint": res, "workload": f"lattice {L}^3 x 4, N={info['n']}, tau={tau}"}), flush=True)
         return
 
@@ -348,7 +352,9 @@ def main():
                 f"correction {rm.correction}")
             del rm
         mixed = {"mixed": mixed}
-    if prec != "fp64":
+    if prec != "fp64" and args.no_reference:
+        mixed = {"switch_iter": res.switch_iter, "correction": res.correction}
+    elif prec != "fp64":
         ref = sp2.density(F, no, lmin, lmax, hub, llb, precision="fp64", **opts)
         err = bsr_diff_frobenius(res.D, ref.D)
         mixed = {"err_vs_fp64_D": err, "fp64_time_to_D_s": ref.time_s, "speedup_vs_fp64": ref.time_s / (sum(times) / len(times)),

@@ -106,7 +106,9 @@ typedef struct {
   double tau_fixed;     /* > 0: the same threshold tau for every iteration */
   double idem_stop;     /* > 0: also stop when e_i <= idem_stop */
   int32_t record_tape;  /* 1: keep the masks and checkpoints needed by vjp / jvp / replay */
-  int32_t n_checkpoints;/* number of X~_i checkpoints in the tape; 0 = ceil(sqrt(n)) */
+  int32_t n_checkpoints;/* number of X~_i checkpoints in the tape; 0 = ceil(sqrt(n)); a checkpoint that
+                           would take the tape beyond min(20% of the device, 30% of free memory) is
+                           skipped (the adjoint then replays from an earlier one) */
   int32_t correct;      /* rounds of the FP64 occupied-subspace correction after the expansion (0 = none);
                            see "Subspace correction" below */
   int32_t corr_purify;  /* FP64 purification squares after each correction round (>= 1; default 2) */
@@ -241,7 +243,9 @@ int sp2_density(sp2_ctx *ctx, const sp2_bsr *F, int64_t n_occ, double lmin, doub
 
 /* Vector-Jacobian product of the recorded (frozen schedule and masks) map
  * F -> D: Fbar = (dL/dF) for L = tr(W D), W symmetric in upper BSR on any
- * pattern.  X~_i are recomputed from the tape's checkpoints.  Each step
+ * pattern.  X~_i are recomputed from the tape's checkpoints; recomputed
+ * iterates are kept for the next steps within min(20% of the device, 30% of
+ * free memory) and recomputed again beyond that.  Each step
  * Xbar <- cb G + cc (X~ G + G X~) runs in the arithmetic the forward used for
  * that X~_i (FP64, or FP32 values with FP32 / BF16x3 products for the
  * low-precision iterations of a mixed run), or in the one the forward's

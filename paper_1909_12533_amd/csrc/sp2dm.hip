@@ -12,6 +12,7 @@
 // The only device -> host traffic per iteration is a handful of scalars and
 // the sizes needed to allocate the next pattern.
 #include <chrono>
+#include <map>
 #include <cstdlib>
 #include <cmath>
 #include <cstdio>
@@ -662,6 +663,9 @@ DMat subspace_correction(Ctx &c, const DMat &F, DMat D, const Tape &ct, int nseq
       C = std::move(co.next);
       sym_diag(c, C, -1.0);
       drop(C, co);
+      if (verbose())
+        std::fprintf(stderr, "[sp2] correction: C = [D, F] nnzb=%lld square %.1f ms\n", (long long)C.pat.nnzb,
+                     1e3 * co.kernel_s);
     }
     // dX~_0 = -(D C - C D) / w = -Delta / w
     DMat dX;
@@ -680,6 +684,9 @@ DMat subspace_correction(Ctx &c, const DMat &F, DMat D, const Tape &ct, int nseq
       cs.delta_norm = std::sqrt(std::fmax(dd.sums[0], 0.0));  // no G: sums[0] = ||D C - C D||_F^2
       dX = std::move(dd.next);
       drop(dX, dd);
+      if (verbose())
+        std::fprintf(stderr, "[sp2] correction: Delta nnzb=%lld ||Delta||=%.3e product %.1f ms\n",
+                     (long long)dX.pat.nnzb, cs.delta_norm, 1e3 * dd.kernel_s);
     }
     // derivative of X_{i+1} = ca I + cb X~_i + cc X~_i^2 along dX~_i
     DMat Xi;
@@ -701,6 +708,9 @@ DMat subspace_correction(Ctx &c, const DMat &F, DMat D, const Tape &ct, int nseq
       cs.flops += jo.sums[4] * fl;
       dX = std::move(jo.next);
       drop(dX, jo);
+      if (verbose())
+        std::fprintf(stderr, "[sp2] correction: derivative step %d/%d nnzb=%lld%s product %.1f ms\n", i + 1, n,
+                     (long long)dX.pat.nnzb, ct.it[i].ckpt ? "" : " (recomputed iterate)", 1e3 * jo.kernel_s);
     }
     cs.step_norm = frob_norm(c, dX);
     DMat P = add_union(c, D, 1.0, dX, 1.0);
@@ -717,6 +727,9 @@ DMat subspace_correction(Ctx &c, const DMat &F, DMat D, const Tape &ct, int nseq
       Buf nrm2 = column(c, so.parts, Pn.pat.nnzb, 3);
       truncate_matrix(c, Pn, nrm2.as<double>(), tau_n, o.trunc_norm, o.coarse_bs);
       P = std::move(Pn);
+      if (verbose())
+        std::fprintf(stderr, "[sp2] correction: purification %d e=%.3e square %.1f ms\n", k, cs.e_last,
+                     1e3 * so.kernel_s);
     }
     D = std::move(P);
     cs.rounds++;
@@ -780,6 +793,7 @@ int run_density(Ctx &c, const sp2_bsr *Fin, int64_t n_occ, double lmin, double l
 
   std::unique_ptr<sp2_tape> tape;
   int ck_every = 1;
+  int64_t tape_budget = 0;  // device bytes for checkpoints; one that does not fit is skipped
   if (o.record_tape) {
     tape.reset(new sp2_tape());
     tape->ctx = &c;
@@ -792,6 +806,9 @@ int run_density(Ctx &c, const sp2_bsr *Fin, int64_t n_occ, double lmin, double l
                         : (o.adjoint_precision == SP2_PREC_FP32 ? M_F32 : M_BF16X3));
     const int nck = o.n_checkpoints > 0 ? o.n_checkpoints : (int)std::ceil(std::sqrt((double)(n_max + 1)));
     ck_every = std::max(1, (int)std::ceil((double)(n_max + 1) / (double)nck));
+    size_t fr = 0, tot = 0;
+    SP2_HIP(hipMemGetInfo(&fr, &tot));
+    tape_budget = (int64_t)std::min(0.2 * (double)tot, 0.3 * (double)fr);
   }
 
   // ---- Algorithm 1 ------------------------------------------------------------------
@@ -842,7 +859,8 @@ int run_density(Ctx &c, const sp2_bsr *Fin, int64_t n_occ, double lmin, double l
         ti.alpha = alph[i];
         poly_coeffs(p[i], alph[i], ti.ca, ti.cb, ti.cc);
       }
-      if (i % ck_every == 0) add_checkpoint(c, *tape, i, X);
+      const int64_t ckb = X.pat.nnzb * (int64_t)BB * (X.pool->prec == P64 ? 8 : 4);
+      if (i % ck_every == 0 && (i == 0 || tape->bytes + ckb <= tape_budget)) add_checkpoint(c, *tape, i, X);
     }
     nnzbv.push_back(X.pat.nnzb);
     max_nnzb = std::max(max_nnzb, X.pat.nnzb);
@@ -1074,12 +1092,6 @@ DMat anticommutator(Ctx &c, const DMat &Gin, const DMat &Xin, const Pattern &out
   return std::move(pair_product(c, X, mx, G, mg, po).next);
 }
 
-int last_ckpt_at_or_below(const Tape &t, int i) {
-  for (int k = i; k >= 0; --k)
-    if (t.it[k].ckpt) return k;
-  fail(SP2_ERR_INVALID_ARG, "tape has no checkpoint");
-}
-
 void check_same_n(const Tape &t, const sp2_bsr *M, const char *what) {
   check_input(M, what);
   if (M->n != t.n) fail(SP2_ERR_INVALID_ARG, std::string(what) + ": dimension differs from the recorded run");
@@ -1092,22 +1104,40 @@ sp2_bsr *run_vjp(Ctx &c, const Tape &t, const sp2_bsr *Win) {
   const int n = t.n_iter;
   DMat Xbar = std::move(W);
   restrict_to(c, Xbar, t.it[n].mask);  // G_n = M_n o W
-  // segment cache of X~_{k} for k in [seg_lo, seg_hi]
-  std::vector<DMat> seg;
-  int seg_lo = 1, seg_hi = 0;
-  for (int i = n; i >= 1; --i) {
-    if (!(i - 1 >= seg_lo && i - 1 <= seg_hi)) {
-      seg.clear();
-      const int c0 = last_ckpt_at_or_below(t, i - 1);
-      seg.push_back(checkpoint_copy(t, c0));
-      for (int k = c0 + 1; k <= i - 1; ++k) seg.push_back(replay_step(c, t, k, seg.back()));
-      seg_lo = c0;
-      seg_hi = i - 1;
+  // X~_{i-1} for i = n..1: from the nearest checkpoint or kept replayed iterate
+  // below it, replaying forward; replayed iterates are kept (to serve the
+  // following, lower i) while they fit in a share of the device memory, else
+  // recomputed when needed again
+  size_t fr = 0, tot = 0;
+  SP2_HIP(hipMemGetInfo(&fr, &tot));
+  const int64_t budget = (int64_t)std::min(0.2 * (double)tot, 0.3 * (double)fr);
+  std::map<int, DMat> kept;
+  int64_t kept_bytes = 0;
+  auto bytes_of = [](const DMat &M) { return M.pat.nnzb * (int64_t)BB * (M.pool->prec == P64 ? 8 : 4); };
+  auto iterate = [&](int k) -> DMat {
+    int b = k;
+    while (b > 0 && !t.it[b].ckpt && !kept.count(b)) --b;
+    DMat X = kept.count(b) ? as_prec(c, kept[b], kept[b].pool->prec) : checkpoint_copy(t, b);
+    for (int j = b + 1; j <= k; ++j) {
+      X = replay_step(c, t, j, X);
+      const int64_t nb = bytes_of(X);
+      if (j < k && kept_bytes + nb <= budget) {
+        kept[j] = as_prec(c, X, X.pool->prec);
+        kept_bytes += nb;
+      }
     }
+    return X;
+  };
+  for (int i = n; i >= 1; --i) {
+    DMat X = iterate(i - 1);
     const TapeIter &ti = t.it[i];
-    Xbar = anticommutator(c, Xbar, seg[(i - 1) - seg_lo], t.it[i - 1].mask, ti.cb, ti.cc, t.step_mode(i - 1));
-    if (i - 1 < seg_hi) seg.resize((i - 1) - seg_lo + 1);  // drop X~ no longer needed
-    seg_hi = i - 1;
+    Xbar = anticommutator(c, Xbar, X, t.it[i - 1].mask, ti.cb, ti.cc, t.step_mode(i - 1));
+    if (verbose()) std::fprintf(stderr, "[sp2] vjp: step %d nnzb=%lld\n", i, (long long)Xbar.pat.nnzb);
+    // iterates at or above i - 1 are not needed any more
+    for (auto it = kept.lower_bound(i - 1); it != kept.end();) {
+      kept_bytes -= bytes_of(it->second);
+      it = kept.erase(it);
+    }
   }
   // Fbar = -(M_0 o Xbar) / w  (Xbar already lives on M_0)
   DMat Fb = compact_values(c, Xbar, P64);
@@ -1127,6 +1157,7 @@ sp2_bsr *run_jvp(Ctx &c, const Tape &t, const sp2_bsr *dFin) {
     const TapeIter &ti = t.it[i];
     DMat nd = anticommutator(c, dX, X, ti.mask, ti.cb, ti.cc, t.step_mode(i - 1));
     dX = std::move(nd);
+    if (verbose()) std::fprintf(stderr, "[sp2] jvp: step %d nnzb=%lld\n", i, (long long)dX.pat.nnzb);
     if (i < t.n_iter) X = replay_step(c, t, i, X);
   }
   return export_bsr(c, dX);
