@@ -241,6 +241,8 @@ def main():
                     help="forward[/adjoint] arithmetics of the adjoint benchmark (errors need fp64 first)")
     ap.add_argument("--switch-tol", type=float, default=None,
                     help="FP64 tail once ||X - X^2||_F < this (default: 0 with the correction, else 1e-3)")
+    ap.add_argument("--n-max-cap", type=int, default=None,
+                    help="stop after this many iterations (a capped run of a workload too long for one call)")
     ap.add_argument("--bounds", default=None,
                     help="homo_ub,lumo_lb known in advance (e.g. from a previous SCF cycle): skips the first run")
     args = ap.parse_args()
@@ -295,6 +297,8 @@ def main():
     mopts = dict(precision=prec, correct=correct, switch_tol=switch_tol) if prec != "fp64" else dict(correct=correct)
     if args.corr_tol is not None:
         mopts["corr_tol"] = args.corr_tol
+    if args.n_max_cap is not None:
+        mopts["n_max_cap"] = args.n_max_cap
 
     def step():
         return sp2.density(F, no, lmin, lmax, hub, llb, **mopts, **opts)
@@ -387,6 +391,7 @@ def main():
             "n": info["n"], "n_occ": no, "tau": tau, "precision": prec,
             "n_iter": res.n_iter, "stop": res.stop_reason, "max_nnzb": res.max_nnzb,
             "alg_tflop_per_step": round(res.alg_flops / 1e12, 3),
+            "device_peak_gb": round(res.correction["device_peak_bytes"] / 1e9, 2),
         },
         "checks": {"trace_err": abs(trD - no), "e_n": float(res.iters["e"][-1]),
                    "homo_est": None if math.isnan(res.homo_est) else res.homo_est,

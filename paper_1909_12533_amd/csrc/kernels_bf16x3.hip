@@ -93,7 +93,10 @@ __global__ __launch_bounds__(TPB, 2) void k_square_tile_bf16x3(TileArgs a) {
 #pragma unroll
     for (int n = 0; n < 4; ++n) acc[m][n] = f4{0, 0, 0, 0};
 
-  // K scan as in the FP64 / FP32 kernel (second pass: operands swapped)
+  // K scan as in the FP64 / FP32 kernel (second pass: operands swapped).  The
+  // slot maps are symmetric (both orientations of a stored block hold its slot),
+  // so the right operand's slots are read along row J of the map: consecutive
+  // K share scalar cache lines.
   const uint32_t *ybits = GEN ? a.ybits : a.bits;
   const uint32_t *bI0 = a.bits + (int64_t)I0 * W, *bI1 = a.bits + (int64_t)(has_i1 ? I0 + 1 : I0) * W;
   const uint32_t *bJ0 = ybits + (int64_t)J0 * W, *bJ1 = ybits + (int64_t)(has_j1 ? J0 + 1 : J0) * W;
@@ -127,12 +130,17 @@ __global__ __launch_bounds__(TPB, 2) void k_square_tile_bf16x3(TileArgs a) {
   int32_t s0 = -1, s1 = -1, s2 = -1, s3 = -1;
   uint32_t g0 = 0u, g1 = 0u, g2 = 0u, g3 = 0u;  // 0x80008000 to negate a staged block
   constexpr uint32_t SGN2 = 0x80008000u;
-// image N (NIMG) or T of the block in slot SL; chunk j * 256 + tid of the image
+// image N (NIMG) or T of the block in slot SL; chunk j * 256 + tid of the
+// image.  An absent block (SL < 0) stages zeros: the staging registers are then
+// written on every path, so the loads of the four operands are issued back to
+// back with no wait on the previous step's loads between them.
 #define SP2_LOAD(R, Q, SL, NIMG)                                                    \
   do {                                                                              \
     if ((SL) >= 0) {                                                                \
       const u32x4 *img_ = (Q) + (int64_t)(SL) * BLK_Q + ((NIMG) ? 0 : IMG_Q) + tid; \
       _Pragma("unroll") for (int j = 0; j < 4; ++j) R[j] = img_[j * TPB];           \
+    } else {                                                                        \
+      _Pragma("unroll") for (int j = 0; j < 4; ++j) R[j] = u32x4{0u, 0u, 0u, 0u};   \
     }                                                                               \
   } while (0)
 #define SP2_ISSUE(KK, KP)                                                                    \
@@ -142,8 +150,8 @@ __global__ __launch_bounds__(TPB, 2) void k_square_tile_bf16x3(TileArgs a) {
     const u32x4 *lq_ = (GEN && (KP)) ? yq : xq, *rq_ = (GEN && (KP)) ? xq : yq;              \
     s0 = __builtin_amdgcn_readfirstlane(li_[(int64_t)I0 * nbr + (KK)]);                      \
     s1 = has_i1 ? __builtin_amdgcn_readfirstlane(li_[(int64_t)(I0 + 1) * nbr + (KK)]) : -1;   \
-    s2 = __builtin_amdgcn_readfirstlane(ri_[(int64_t)(KK) * nbr + J0]);                      \
-    s3 = has_j1 ? __builtin_amdgcn_readfirstlane(ri_[(int64_t)(KK) * nbr + J0 + 1]) : -1;    \
+    s2 = __builtin_amdgcn_readfirstlane(ri_[(int64_t)J0 * nbr + (KK)]);                      \
+    s3 = has_j1 ? __builtin_amdgcn_readfirstlane(ri_[(int64_t)(J0 + 1) * nbr + (KK)]) : -1;  \
     const bool n0_ = I0 <= (KK), n1_ = I0 + 1 <= (KK), n2_ = (KK) > J0, n3_ = (KK) > J0 + 1; \
     if (GEN) {                                                                               \
       const bool la_ = (KP) ? a.yanti : a.xanti, ra_ = (KP) ? a.xanti : a.yanti;             \
@@ -159,15 +167,13 @@ __global__ __launch_bounds__(TPB, 2) void k_square_tile_bf16x3(TileArgs a) {
     SP2_LOAD(r3, rq_, s3, n3_);                                                              \
   } while (0)
 // chunk j * 256 + tid: plane j / 2, row ((j & 1) * 256 + tid) / 8, 16-byte column chunk tid % 8
-#define SP2_STORE(R, SL, O, G)                                                           \
-  do {                                                                                   \
-    if ((SL) >= 0) {                                                                     \
-      _Pragma("unroll") for (int j = 0; j < 4; ++j) {                                    \
-        const int pq_ = ((j & 1) << 8) + tid;                                            \
-        uint16_t *d_ = &L[O][j >> 1][(pq_ >> 3) * LDH + (pq_ & 7) * 8];                   \
-        *reinterpret_cast<u32x4 *>(d_) = GEN ? (R[j] ^ u32x4{(G), (G), (G), (G)}) : R[j]; \
-      }                                                                                  \
-    }                                                                                    \
+#define SP2_STORE(R, O, G)                                                             \
+  do {                                                                                 \
+    _Pragma("unroll") for (int j = 0; j < 4; ++j) {                                    \
+      const int pq_ = ((j & 1) << 8) + tid;                                            \
+      uint16_t *d_ = &L[O][j >> 1][(pq_ >> 3) * LDH + (pq_ & 7) * 8];                   \
+      *reinterpret_cast<u32x4 *>(d_) = GEN ? (R[j] ^ u32x4{(G), (G), (G), (G)}) : R[j]; \
+    }                                                                                  \
   } while (0)
 
   const int l16 = lane & 15, g = lane >> 4;
@@ -177,10 +183,10 @@ __global__ __launch_bounds__(TPB, 2) void k_square_tile_bf16x3(TileArgs a) {
   while (K >= 0) {
     const int32_t c0 = s0, c1 = s1, c2 = s2, c3 = s3;
     __syncthreads();  // previous planes fully consumed
-    SP2_STORE(r0, c0, 0, g0);
-    SP2_STORE(r1, c1, 1, g1);
-    SP2_STORE(r2, c2, 2, g2);
-    SP2_STORE(r3, c3, 3, g3);
+    SP2_STORE(r0, 0, g0);
+    SP2_STORE(r1, 1, g1);
+    SP2_STORE(r2, 2, g2);
+    SP2_STORE(r3, 3, g3);
     __syncthreads();
     const int Kn = next_k();
     if (Kn >= 0) SP2_ISSUE(Kn, kpass);  // next K's images in flight during the MFMAs

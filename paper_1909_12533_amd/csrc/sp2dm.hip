@@ -233,6 +233,14 @@ DMat borrow_matrix(Ctx &c, const sp2_bsr *M, const char *what) {
   return d;
 }
 
+// Truncation and masking keep the pool and drop positions from the pattern; a
+// pool left with many unused slots is copied to a contiguous one, so that the
+// dropped blocks do not stay resident through the next square (and the BF16x3
+// images, packed per slot, cover only the kept blocks).
+DMat compact_if_sparse(Ctx &c, DMat X) {
+  if (X.pool && X.pat.nnzb < X.pool->nslots - X.pool->nslots / 8) return compact_values(c, X, X.pool->prec);
+  return X;
+}
 // ------------------------------------------------------------------ steps
 // BF16x3 operand images of X (32 KB per pool slot), or an empty buffer for the
 // other arithmetics
@@ -957,6 +965,8 @@ int run_density(Ctx &c, const sp2_bsr *Fin, int64_t n_occ, double lmin, double l
       Xn = compact_values(c, Xn, P64);
       sym_diag(c, Xn, 1.0);  // the FP64 tail starts from the symmetric part
       switch_iter = i + 1;
+    } else {
+      Xn = compact_if_sparse(c, std::move(Xn));
     }
     X = std::move(Xn);
     c.sync();
@@ -1061,8 +1071,13 @@ DMat replay_step(Ctx &c, const Tape &t, int i, const DMat &Xprev) {
   SquareOut so = square_step(c, Xprev, m, tp.mode, Xprev.pool->prec, ti.ca, ti.cb, ti.cc);
   DMat Xn = std::move(so.next);
   restrict_to(c, Xn, ti.mask);
-  if (Xn.pool->prec != ti.prec) Xn = compact_values(c, Xn, ti.prec);
-  return Xn;
+  if (Xn.pool->prec != ti.prec) {
+    // the switch to the FP64 tail: the forward continues from the symmetric part
+    Xn = compact_values(c, Xn, ti.prec);
+    if (ti.prec == P64) sym_diag(c, Xn, 1.0);
+    return Xn;
+  }
+  return compact_if_sparse(c, std::move(Xn));
 }
 
 DMat checkpoint_copy(const Tape &t, int i) {
@@ -1171,6 +1186,10 @@ sp2_bsr *run_replay(Ctx &c, const Tape &t, const sp2_bsr *Fin) {
   restrict_to(c, X, t.it[0].mask);
   if (t.it[0].prec == P32) X = compact_values(c, X, P32);
   for (int i = 1; i <= t.n_iter; ++i) X = replay_step(c, t, i, X);
+  if (X.pool->prec == P32) {  // as the forward: a low-precision result is returned symmetrized
+    X = compact_values(c, X, P32);
+    sym_diag(c, X, 1.0);
+  }
   return export_bsr(c, X);
 }
 

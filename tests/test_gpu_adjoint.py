@@ -123,3 +123,40 @@ def test_autograd_function_matches_finite_differences(gpu_lib):
     assert torch.equal(Dp.row_ptr, rp) and torch.equal(Dp.col_idx, ci)
     rhs = float((g * (Dp.val - Dm.val)).sum()) / (2 * h)
     assert lhs == pytest.approx(rhs, rel=1e-6)
+
+
+
+def test_mixed_tape_adjoint_arithmetic(gpu_lib):
+    """A BF16x3 forward (with its FP64 tail) records BF16x3 steps; its VJP and
+    JVP run them in BF16x3 by default and in FP32 or FP64 with
+    adjoint_precision.  Replay reproduces the forward bit for bit; on the one
+    recorded trajectory the three gradients agree to the arithmetic's roundoff,
+    each passes the dot-product test, and all are close to the gradient of the
+    FP64 forward."""
+    sp2 = gpu_lib
+    Fh, info = lattice_fock(6, seed=0)
+    no = info["n_occ"]
+    lmin, lmax = O.gershgorin_bounds(bsr_to_dense(Fh))
+    F = sp2.BsrMatrix.from_host(Fh)
+    kw = dict(accel=True, trunc_norm="frobinf", tau_fixed=1e-2, coarse_bs=128, record_tape=True)
+    Wh = random_sym_on_pattern(Fh, 1.0, seed=2)
+    dFh = random_sym_on_pattern(Fh, 1e-3, seed=1)
+    W, dF = sp2.BsrMatrix.from_host(Wh), sp2.BsrMatrix.from_host(dFh)
+    g64 = to_dense(sp2.density(F, no, lmin, lmax, -0.37, 0.34, **kw).tape.vjp(W))
+    # The JVP and VJP steps use the stored iterates as symmetric matrices; the
+    # BF16x3 iterates' diagonal blocks carry antisymmetric rounding of relative
+    # size ~2^-16, so the two are transposes of each other only to that level,
+    # whatever the adjoint arithmetic.
+    g, dot_tol = {}, {-1: 1e-3, "fp32": 2e-5, "fp64": 2e-5}
+    for adj in (-1, "fp32", "fp64"):
+        r = sp2.density(F, no, lmin, lmax, -0.37, 0.34, precision="bf16x3", adjoint_precision=adj, **kw)
+        assert r.switch_iter > 0
+        if adj == -1:  # the frozen map, FP64 switch included, reproduces the forward
+            assert np.array_equal(to_dense(r.tape.replay(F)), to_dense(r.D))
+        g[adj] = to_dense(r.tape.vjp(W))
+        jv = to_dense(r.tape.jvp(dF))
+        lhs, rhs = float(np.sum(bsr_to_dense(Wh) * jv)), float(np.sum(g[adj] * bsr_to_dense(dFh)))
+        assert lhs == pytest.approx(rhs, rel=dot_tol[adj])
+    assert rel(g[-1], g["fp64"]) <= 1e-3
+    assert rel(g["fp32"], g["fp64"]) <= 1e-5
+    assert rel(g["fp64"], g64) <= 5e-2
