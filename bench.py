@@ -240,7 +240,8 @@ def main():
     ap.add_argument("--adjoint-runs", default="fp64,fp32,bf16x3,bf16x3/fp32",
                     help="forward[/adjoint] arithmetics of the adjoint benchmark (errors need fp64 first)")
     ap.add_argument("--switch-tol", type=float, default=None,
-                    help="FP64 tail once ||X - X^2||_F < this (default: 0 with the correction, else 1e-3)")
+                    help="FP64 tail once ||X - X^2||_F < this (default: 0 with the correction, else 1e-3; "
+                         "< 0: no FP64 tail)")
     ap.add_argument("--n-max-cap", type=int, default=None,
                     help="stop after this many iterations (a capped run of a workload too long for one call)")
     ap.add_argument("--bounds", default=None,

@@ -98,7 +98,8 @@ typedef struct {
 typedef struct {
   int32_t accel;        /* 1: SP2ACC (scale-and-fold), 0: SP2 (alpha_i = 1, n_min = 1) */
   int32_t precision;    /* SP2_PREC_* */
-  double switch_tol;    /* mixed precision: FP64 from the first square after e_i < switch_tol */
+  double switch_tol;    /* mixed precision: FP64 from the first square after e_i < switch_tol;
+                           < 0: no FP64 tail, the low precision to its own stopping criterion */
   int32_t trunc_norm;   /* SP2_TRUNC_* */
   int32_t n_max_cap;    /* cap of n_max, and n_max of the trace-correcting run (<= 1000) */
   int64_t coarse_bs;    /* Frob-Inf submatrix size, a multiple of 64 (paper: 4096) */

@@ -772,8 +772,8 @@ int run_density(Ctx &c, const sp2_bsr *Fin, int64_t n_occ, double lmin, double l
   if (o.n_max_cap < 1 || o.n_max_cap > 1000) fail(SP2_ERR_INVALID_ARG, "n_max_cap must be in [1, 1000]");
   if (o.trunc_norm == SP2_TRUNC_FROBINF && (o.coarse_bs <= 0 || o.coarse_bs % B))
     fail(SP2_ERR_INVALID_ARG, "coarse_bs must be a positive multiple of 64");
-  if (!(o.gamma >= 0.0) || !(o.tau_fixed >= 0.0) || !(o.switch_tol >= 0.0) || !(o.idem_stop >= 0.0))
-    fail(SP2_ERR_INVALID_ARG, "tolerances must be >= 0");
+  if (!(o.gamma >= 0.0) || !(o.tau_fixed >= 0.0) || std::isnan(o.switch_tol) || !(o.idem_stop >= 0.0))
+    fail(SP2_ERR_INVALID_ARG, "tolerances must be >= 0 (switch_tol: any number)");
   if (st && st->capacity < o.n_max_cap + 1) fail(SP2_ERR_INVALID_ARG, "stats capacity < n_max_cap + 1");
   if (tape_out && !o.record_tape) fail(SP2_ERR_INVALID_ARG, "a tape needs record_tape = 1");
   if (o.correct < 0 || o.correct > 8) fail(SP2_ERR_INVALID_ARG, "correct must be in [0, 8]");
@@ -784,9 +784,9 @@ int run_density(Ctx &c, const sp2_bsr *Fin, int64_t n_occ, double lmin, double l
   if (o.adjoint_precision < -1 || o.adjoint_precision > 2) fail(SP2_ERR_INVALID_ARG, "unknown adjoint_precision");
   const int lowmode = o.precision == SP2_PREC_FP32 ? M_F32 : (o.precision == SP2_PREC_BF16X3 ? M_BF16X3 : M_F64);
   const bool corr = o.correct > 0;
-  // with the correction and no switch tolerance the whole expansion stays in
-  // the low precision and stops by its own criterion
-  const bool low_to_end = corr && !(o.switch_tol > 0.0);
+  // with the correction and no switch tolerance, or with a negative one, the
+  // whole expansion stays in the low precision and stops by its own criterion
+  const bool low_to_end = (corr && !(o.switch_tol > 0.0)) || o.switch_tol < 0.0;
 
   auto t_start = std::chrono::steady_clock::now();
   c.peak_bytes = c.live_bytes;
@@ -953,6 +953,7 @@ int run_density(Ctx &c, const sp2_bsr *Fin, int64_t n_occ, double lmin, double l
     }
     DMat Xn = std::move(so.next);
     const int64_t nout = Xn.pat.nnzb;
+    X = DMat{};  // X~_i is not needed any more: release it before X_{i+1} is compacted
     {
       Buf nrm2 = column(c, so.parts, nout, 3);
       TruncResult tr = truncate_matrix(c, Xn, nrm2.as<double>(), sch.tau[i + 1], o.trunc_norm, o.coarse_bs);

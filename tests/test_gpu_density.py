@@ -161,3 +161,28 @@ def test_mixed_bf16x3_reports_error(gpu_lib):
     print(f"mixed bf16x3 vs fp64: ||dD||_F = {err:.3e}, n = {rb.n_iter} vs {r64.n_iter}, switch {rb.switch_iter}")
     assert err <= 5e-2
     assert abs(np.trace(to_dense(rb.D)) - no) <= 1e-6
+
+
+def test_low_precision_to_the_end(gpu_lib):
+    """switch_tol < 0: every square in FP32, the stopping criterion evaluated on
+    the FP32 e_i; the result is symmetric, has the right trace, is idempotent to
+    FP32 level and close to the FP64 run; no homo/lumo estimate comes from
+    low-precision e_i alone."""
+    sp2 = gpu_lib
+    Fh, info = lattice_fock(8, seed=0)
+    Fd = bsr_to_dense(Fh)
+    no = info["n_occ"]
+    lmin, lmax = O.gershgorin_bounds(Fd)
+    F = sp2.BsrMatrix.from_host(Fh)
+    kw = dict(trunc_norm="frobinf", tau_fixed=1e-6, coarse_bs=512)
+    r64 = sp2.density(F, no, lmin, lmax, -0.31, 0.33, **kw)
+    r = sp2.density(F, no, lmin, lmax, -0.31, 0.33, precision="fp32", switch_tol=-1.0, **kw)
+    assert r.status == 0 and r.stop_reason == "criterion"
+    assert r.switch_iter == -1
+    assert set(r.iters["precision"]) == {1}
+    D = to_dense(r.D)
+    assert np.array_equal(D, D.T)
+    assert abs(np.trace(D) - no) <= 1e-3
+    assert np.linalg.norm(D @ D - D) <= 5e-3
+    assert np.linalg.norm(D - to_dense(r64.D)) <= 5e-3
+    assert np.isnan(r.homo_est) and np.isnan(r.lumo_est)
