@@ -367,9 +367,14 @@ def main():
                  "correction": res.correction}
         log(f"mixed {prec}: ||D - D_fp64||_F = {err:.3e}, FP64 run {ref.time_s:.3f} s, speedup "
             f"{mixed['speedup_vs_fp64']:.2f}x, switch at {res.switch_iter}, correction {res.correction}")
-    n, rp, ci, v = res.D.to_host()
-    diag = np.array([np.trace(v[b]) for b in range(len(ci)) if ci[b] == np.searchsorted(rp, b, side="right") - 1])
-    trD = float(diag.sum())
+    # tr D from the diagonal blocks (the first block of each block row when present), on the device
+    D = res.D
+    first = D.row_ptr[:-1]
+    has = first < D.row_ptr[1:]
+    rows = torch.arange(D.nbr, device=D.device)[has]
+    dpos = first[has]
+    dpos = dpos[D.col_idx[dpos].to(torch.int64) == rows]
+    trD = float(torch.diagonal(D.val[dpos], dim1=1, dim2=2).sum())
     line = {
         "metric": "time-to-D (s), block-sparse TFLOP/s; mixed vs FP64 at ||D-D_ref||_F<=1e-5",
         "value": round(value, 4),
