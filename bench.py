@@ -217,6 +217,41 @@ def adjoint_bench(sp2, F, Fh, no, lmin, lmax, hub, llb, opts, precisions):
     return out
 
 
+def norm_study(sp2, sizes, half_bw=300, coarse=(128, 512)):
+    """The paper's norm comparison (section "Upper bounds for the spectral
+    norm"): symmetric banded matrices with entries U(0, 1e-3) and bandwidth
+    2 x 300 + 1, plain and randomly permuted; Frobenius and Frob-Inf norms
+    (coarse submatrices of 128 and 512 rows, the multiples of 64 nearest the
+    paper's 100 and 500) by the library's norm kernels, the spectral norm by a
+    CPU Lanczos solve (invariant under the permutation)."""
+    import scipy.sparse.linalg as spla
+    import torch
+
+    from fockgen import banded_sym, sparse_to_bsr
+
+    out = []
+    for n in sizes:
+        A = banded_sym(n, half_bw=half_bw, seed=0)
+        spec = float(abs(spla.eigsh(A, k=1, which="LM", return_eigenvectors=False)[0]))
+        for perm in (False, True):
+            M = sparse_to_bsr(banded_sym(n, half_bw=half_bw, seed=0, permute=perm) if perm else A)
+            D = sp2.BsrMatrix.from_host(M, "cuda:0")
+            row = {"n": n, "permuted": perm, "nnzb": M.nnzb, "spectral": spec}
+            for cbs in coarse:
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                f, m = sp2.matrix_norms(D, cbs)
+                torch.cuda.synchronize()
+                row["frobenius"] = f
+                row[f"frobinf_{cbs}"] = m
+                row[f"gpu_ms_{cbs}"] = round(1e3 * (time.perf_counter() - t0), 3)
+            log(f"norms n={n} permuted={perm}: spectral {spec:.4g} Frobenius {row['frobenius']:.4g} "
+                + " ".join(f"FrobInf({c}) {row[f'frobinf_{c}']:.4g}" for c in coarse))
+            out.append(row)
+            del D
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -242,6 +277,9 @@ def main():
     ap.add_argument("--switch-tol", type=float, default=None,
                     help="FP64 tail once ||X - X^2||_F < this (default: 0 with the correction, else 1e-3; "
                          "< 0: no FP64 tail)")
+    ap.add_argument("--norms", default=None,
+                    help="instead of the expansion benchmark: the norm comparison (spectral vs Frobenius vs "
+                         "Frob-Inf) on banded and permuted matrices of these sizes, e.g. 1024,2048,4096")
     ap.add_argument("--n-max-cap", type=int, default=None,
                     help="stop after this many iterations (a capped run of a workload too long for one call)")
     ap.add_argument("--bounds", default=None,
@@ -257,6 +295,11 @@ def main():
 
     from fockgen import lattice_fock
     from paper_1909_12533_amd import sp2
+
+    if args.norms:
+        res = norm_study(sp2, [int(x) for x in args.norms.split(",")])
+        print(json.dumps({"norm_study": res}), flush=True)
+        return
 
     cfg = dict(CONFIGS[args.config])
     if args.precision:

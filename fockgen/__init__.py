@@ -295,6 +295,52 @@ def random_sym_bsr(n, density, seed=0, bs=BS, std=1.0, keep_diag=True):
     return BSR(n, row_ptr, J.astype(np.int32), val, bs)
 
 
+def banded_sym(n, half_bw=300, hi=1e-3, seed=0, permute=False):
+    """Symmetric banded matrix (scipy CSR) with entries U(0, hi) on
+    |i - j| <= half_bw (bandwidth 2 half_bw + 1), the test matrices of the
+    paper's norm comparison (section "Upper bounds for the spectral norm");
+    with ``permute`` the rows and columns are permuted by one seeded random
+    permutation (P A P^T)."""
+    import scipy.sparse as sps
+
+    rng = np.random.default_rng(seed)
+    i = np.repeat(np.arange(n), half_bw + 1)
+    j = i + np.tile(np.arange(half_bw + 1), n)
+    keep = j < n
+    i, j = i[keep], j[keep]
+    v = rng.uniform(0.0, hi, size=i.shape[0])
+    off = i != j
+    A = sps.coo_matrix((np.concatenate([v, v[off]]), (np.concatenate([i, j[off]]), np.concatenate([j, i[off]]))),
+                       shape=(n, n)).tocsr()
+    if permute:
+        p = np.random.default_rng(seed + 1).permutation(n)
+        A = A[p][:, p].tocsr()
+    return A
+
+
+def sparse_to_bsr(A, bs=BS):
+    """Upper BSR of a symmetric scipy sparse matrix, without a dense copy;
+    diagonal blocks are always stored."""
+    A = A.tocoo()
+    A.sum_duplicates()  # every entry then has its own position in its block
+    n = A.shape[0]
+    nbr = (n + bs - 1) // bs
+    bi, bj = A.row // bs, A.col // bs
+    up = bj >= bi
+    r, c, v, bi, bj = A.row[up], A.col[up], A.data[up], bi[up], bj[up]
+    ids = np.unique(np.concatenate([bi.astype(np.int64) * nbr + bj, np.arange(nbr, dtype=np.int64) * (nbr + 1)]))
+    I, J = ids // nbr, ids % nbr
+    pos = np.searchsorted(ids, bi.astype(np.int64) * nbr + bj)
+    flat = (pos * bs + (r % bs)) * bs + (c % bs)
+    order = np.argsort(flat, kind="stable")  # write in memory order
+    val = np.zeros(ids.shape[0] * bs * bs)
+    val[flat[order]] = v[order]
+    val = val.reshape(ids.shape[0], bs, bs)
+    row_ptr = np.zeros(nbr + 1, dtype=np.int64)
+    np.add.at(row_ptr, I + 1, 1)
+    return BSR(n, np.cumsum(row_ptr), J.astype(np.int32), val, bs)
+
+
 def _zero_padding(n, nbr, bs, I, J, val):
     pad = nbr * bs - n
     if pad == 0:

@@ -323,6 +323,17 @@ int sp2_pair_product(sp2_ctx *ctx, const sp2_bsr *X, const sp2_bsr *Y, const sp2
 int sp2_truncate(sp2_ctx *ctx, const sp2_bsr *X, double tau, int norm, int64_t coarse_bs,
                  sp2_bsr **Xt_out, double err[2]);
 
+/* Norms of the symmetric matrix A held by its upper blocks (section "Upper
+ * bounds for the spectral norm"): *frob = ||A||_F of the full matrix and
+ * *frobinf = ||A||_M, the Frob-Inf mixed norm: the largest row sum of the
+ * matrix of Frobenius norms of the coarse_bs x coarse_bs submatrices of the
+ * full matrix (the last ones smaller when coarse_bs does not divide n), an
+ * upper bound of the spectral norm.  coarse_bs is a positive multiple of 64
+ * with at most 16384 submatrices per row (checked only when frobinf is
+ * requested); either output pointer may be NULL.  Both are accumulated in
+ * FP64 in a fixed order (bitwise reproducible). */
+int sp2_matrix_norms(sp2_ctx *ctx, const sp2_bsr *A, int64_t coarse_bs, double *frob, double *frobinf);
+
 /* Copy a library matrix into caller buffers (device pointers of sizes
  * nbr + 1, nnzb, nnzb * 64 * 64). */
 int sp2_bsr_copy(sp2_ctx *ctx, const sp2_bsr *src, int64_t *row_ptr, int32_t *col_idx, double *val);

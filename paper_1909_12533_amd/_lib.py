@@ -25,7 +25,7 @@ EXPORTS = [
     "sp2_version", "sp2_options_default", "sp2_create", "sp2_destroy", "sp2_set_allocator", "sp2_trim",
     "sp2_last_error", "sp2_gershgorin", "sp2_density", "sp2_vjp", "sp2_jvp", "sp2_replay", "sp2_tape_info",
     "sp2_square_step", "sp2_truncate", "sp2_bsr_copy", "sp2_bsr_free", "sp2_tape_free", "sp2_schedule",
-    "sp2_homo_lumo", "sp2_pair_product",
+    "sp2_homo_lumo", "sp2_pair_product", "sp2_matrix_norms",
 ]
 
 
@@ -159,6 +159,8 @@ def load(path: str = LIB_PATH):
     lib.sp2_truncate.restype = C.c_int
     lib.sp2_truncate.argtypes = [C.c_void_p, P(sp2_bsr), C.c_double, C.c_int, C.c_int64, P(P(sp2_bsr)),
                                  P(C.c_double)]
+    lib.sp2_matrix_norms.restype = C.c_int
+    lib.sp2_matrix_norms.argtypes = [C.c_void_p, P(sp2_bsr), C.c_int64, P(C.c_double), P(C.c_double)]
     lib.sp2_bsr_copy.restype = C.c_int
     lib.sp2_bsr_copy.argtypes = [C.c_void_p, P(sp2_bsr), C.c_void_p, C.c_void_p, C.c_void_p]
     lib.sp2_bsr_free.restype = None

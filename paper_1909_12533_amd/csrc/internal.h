@@ -173,6 +173,9 @@ void launch_gather(Ctx &c, const void *src, int src_prec, const int32_t *slot, i
                    int dst_prec);
 void launch_reduce_parts(Ctx &c, const double *parts, int64_t nrows, int ncols, double *out);
 void launch_block_norms(Ctx &c, const void *pool, int prec, const int32_t *slot, int64_t nblocks, double *nrm2);
+// pair: nc (nc + 1) / 2 doubles (packed upper coarse squared norms); rowsum: nc
+void launch_coarse_rowsums(Ctx &c, const int64_t *row_ptr, const int32_t *col_idx, const double *nrm2, int nbr,
+                           int cb, int nc, double *pair, double *rowsum);
 void launch_update(Ctx &c, const void *xpool, int xprec, const int32_t *xidxmap, int nbr, const int32_t *out_row,
                    const int32_t *out_col, int64_t nout, void *spool, int sprec, double ca, double cb, double cc,
                    int64_t n, double *parts);

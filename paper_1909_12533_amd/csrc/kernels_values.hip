@@ -220,6 +220,57 @@ __global__ void k_update(const TX *xpool, const int32_t *xidxmap, int nbr, const
   if (threadIdx.x == 0) parts[w * NPART + 3] = t;
 }
 
+// Frob-Inf mixed norm (section "Upper bounds for the spectral norm") of a
+// symmetric matrix held by its upper blocks, in two deterministic passes.
+// Coarse submatrices are cb x cb blocks; coarse (R, S), R <= S, gets the
+// squared Frobenius norm of its part of the full matrix: inside a diagonal
+// coarse submatrix an off-diagonal block stands for itself and its mirror
+// (weight 2), elsewhere each stored block counts once (its mirror lies in
+// (S, R)).  One thread per upper coarse pair sums, row by row, the blocks
+// whose column falls in S's range (a contiguous run of the sorted row).
+__global__ void k_coarse_pairs(const int64_t *row_ptr, const int32_t *col_idx, const double *nrm2, int nbr, int cb,
+                               int nc, int64_t npairs, double *pair) {
+  const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (q >= npairs) return;
+  // q -> (R, S) with R <= S, row-major over the upper triangle of nc x nc:
+  // row R starts at P(R) = R (2 nc - R + 1) / 2
+  auto start = [nc](int64_t r) { return r * (2 * (int64_t)nc - r + 1) / 2; };
+  const double d = 2.0 * nc + 1.0;
+  int64_t R = (int64_t)((d - sqrt(fmax(d * d - 8.0 * (double)q, 0.0))) / 2.0);
+  R = R < 0 ? 0 : (R >= nc ? nc - 1 : R);
+  while (R > 0 && start(R) > q) --R;
+  while (R + 1 < nc && start(R + 1) <= q) ++R;
+  const int S = (int)(R + (q - start(R)));
+  const int jlo = S * cb, jhi = min(nbr, (S + 1) * cb);
+  double sum = 0.0;
+  for (int I = (int)R * cb; I < min(nbr, ((int)R + 1) * cb); ++I) {
+    int64_t lo = row_ptr[I], hi = row_ptr[I + 1];
+    // first position with col >= jlo
+    while (lo < hi) {
+      const int64_t mid = (lo + hi) / 2;
+      if (col_idx[mid] < jlo) lo = mid + 1;
+      else hi = mid;
+    }
+    for (int64_t b = lo; b < row_ptr[I + 1] && col_idx[b] < jhi; ++b)
+      sum += (R == S && col_idx[b] != I) ? 2.0 * nrm2[b] : nrm2[b];
+  }
+  pair[q] = sum;
+}
+
+// row sums of the coarse Frobenius norms: rowsum[R] = sum_S sqrt(c(R, S)),
+// c symmetric, read from the packed upper triangle
+__global__ void k_coarse_rowsum(const double *pair, int nc, double *rowsum) {
+  const int R = blockIdx.x * blockDim.x + threadIdx.x;
+  if (R >= nc) return;
+  double s = 0.0;
+  for (int S = 0; S < nc; ++S) {
+    const int a = min(R, S), b = max(R, S);
+    const int64_t q = (int64_t)a * nc - (int64_t)a * (a - 1) / 2 + (b - a);
+    s += sqrt(pair[q]);
+  }
+  rowsum[R] = s;
+}
+
 }  // namespace
 
 void launch_check_finite(Ctx &c, const double *v, int64_t n, int32_t *flag) {
@@ -323,6 +374,17 @@ void launch_update(Ctx &c, const void *xpool, int xprec, const int32_t *xidxmap,
                                                     (float *)spool, ca, cb, cc, n, parts);
   else
     fail(SP2_ERR_INVALID_ARG, "update: mixed pool precisions");
+  SP2_LAUNCH_CHECK();
+}
+
+void launch_coarse_rowsums(Ctx &c, const int64_t *row_ptr, const int32_t *col_idx, const double *nrm2, int nbr,
+                           int cb, int nc, double *pair, double *rowsum) {
+  if (nc <= 0) return;
+  const int64_t npairs = (int64_t)nc * (nc + 1) / 2;
+  k_coarse_pairs<<<(unsigned)((npairs + TPB - 1) / TPB), TPB, 0, c.stream>>>(row_ptr, col_idx, nrm2, nbr, cb, nc,
+                                                                             npairs, pair);
+  SP2_LAUNCH_CHECK();
+  k_coarse_rowsum<<<(unsigned)((nc + TPB - 1) / TPB), TPB, 0, c.stream>>>(pair, nc, rowsum);
   SP2_LAUNCH_CHECK();
 }
 

@@ -1508,6 +1508,33 @@ int sp2_truncate(sp2_ctx *ctx, const sp2_bsr *Xin, double tau, int norm, int64_t
   });
 }
 
+int sp2_matrix_norms(sp2_ctx *ctx, const sp2_bsr *Ain, int64_t coarse_bs, double *frob, double *frobinf) {
+  return guarded(ctx, [&]() {
+    if (frobinf && (coarse_bs <= 0 || coarse_bs % B))
+      fail(SP2_ERR_INVALID_ARG, "coarse_bs must be a positive multiple of 64");
+    DMat A = borrow_matrix(*ctx, Ain, "A");
+    check_finite(*ctx, Ain->val, Ain->nnzb * (int64_t)BB, "A");
+    if (frob) *frob = frob_norm(*ctx, A);
+    if (frobinf) {
+      *frobinf = 0.0;
+      const int nbr = (int)A.pat.nbr, cb = (int)(coarse_bs / B);
+      const int nc = (nbr + cb - 1) / cb;
+      if (nc > 16384) fail(SP2_ERR_INVALID_ARG, "coarse_bs too small for this matrix (more than 16384 submatrices per row)");
+      if (A.pat.nnzb > 0 && nc > 0) {
+        Buf nrm2 = norms_of(*ctx, A);
+        Buf pair = ctx->alloc(sizeof(double) * ((size_t)nc * (nc + 1) / 2));
+        Buf rows = ctx->alloc(sizeof(double) * nc);
+        launch_coarse_rowsums(*ctx, A.pat.row_ptr.as<int64_t>(), A.pat.col_idx.as<int32_t>(), nrm2.as<double>(), nbr,
+                              cb, nc, pair.as<double>(), rows.as<double>());
+        std::vector<double> h(nc);
+        ctx->d2h(h.data(), rows.p, sizeof(double) * nc);
+        for (double v : h) *frobinf = std::max(*frobinf, v);
+      }
+    }
+    return SP2_OK;
+  });
+}
+
 int sp2_bsr_copy(sp2_ctx *ctx, const sp2_bsr *src, int64_t *row_ptr, int32_t *col_idx, double *val) {
   return guarded(ctx, [&]() {
     if (!src) fail(SP2_ERR_INVALID_ARG, "NULL matrix");

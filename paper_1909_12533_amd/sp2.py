@@ -395,6 +395,17 @@ def pair_product(X: BsrMatrix, Y: BsrMatrix, G: BsrMatrix | None = None, sign=1,
     return r, list(sums)
 
 
+def matrix_norms(A: BsrMatrix, coarse_bs=4096, ctx: Context | None = None):
+    """(||A||_F, ||A||_M) of the symmetric matrix held by A's upper blocks;
+    ||A||_M is the Frob-Inf norm with coarse_bs x coarse_bs submatrices."""
+    ctx = ctx or context(A.device.index)
+    f, m = C.c_double(), C.c_double()
+    s = A._struct()
+    ctx._check(ctx.lib.sp2_matrix_norms(ctx.h, C.byref(s), int(coarse_bs), C.byref(f), C.byref(m)))
+    ctx.trim()
+    return f.value, m.value
+
+
 def truncate(X: BsrMatrix, tau: float, norm="frobinf", coarse_bs=4096, ctx: Context | None = None):
     """Truncation with ||E|| <= tau; returns (X~, (||E||_F, ||E||_M))."""
     ctx = ctx or context(X.device.index)

@@ -157,3 +157,32 @@ def test_square_step_bf16x3(gpu_lib, n, dens, seed):
     assert np.all(err <= bound)
     # and it is genuinely better than a plain bf16 product (error ~2^-8)
     assert np.max(err / (Xa @ Xa + 1e-30)) < 2.0 ** -12
+
+
+@pytest.mark.parametrize("cbs", [64, 128, 256, 4096])
+@pytest.mark.parametrize("n,dens,seed", [(64, 1.0, 0), (1000, 0.35, 2), (1500, 0.12, 3)])
+def test_matrix_norms(gpu_lib, n, dens, seed, cbs):
+    """Frobenius and Frob-Inf norms of the full symmetric matrix against the
+    oracle's definitions (ragged last coarse submatrix included), and the
+    Frob-Inf norm bounds the spectral norm."""
+    sp2 = gpu_lib
+    Mh = _spread_bsr(n, seed=seed, dens=dens)
+    Md = bsr_to_dense(Mh)
+    f, m = sp2.matrix_norms(sp2.BsrMatrix.from_host(Mh), cbs)
+    assert f == pytest.approx(O.frobenius_norm(Md), rel=1e-12)
+    assert m == pytest.approx(O.frob_inf_norm(Md, cbs), rel=1e-12)
+    assert O.spectral_norm_sym(Md) <= m * (1 + 1e-12)
+
+
+@pytest.mark.parametrize("permute", [False, True])
+def test_matrix_norms_banded(gpu_lib, permute):
+    """The banded test matrices of the norm comparison, plain and permuted."""
+    from fockgen import banded_sym, sparse_to_bsr
+
+    sp2 = gpu_lib
+    A = banded_sym(1500, half_bw=150, seed=4, permute=permute)
+    Ad = A.toarray()
+    for cbs in (128, 512):
+        f, m = sp2.matrix_norms(sp2.BsrMatrix.from_host(sparse_to_bsr(A)), cbs)
+        assert f == pytest.approx(O.frobenius_norm(Ad), rel=1e-12)
+        assert m == pytest.approx(O.frob_inf_norm(Ad, cbs), rel=1e-12)
