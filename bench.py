@@ -217,6 +217,36 @@ def adjoint_bench(sp2, F, Fh, no, lmin, lmax, hub, llb, opts, precisions):
     return out
 
 
+def storage_bench(sp2, F, no, lmin, lmax, hub, llb, opts, prec):
+    """Symmetric vs general storage (the paper's comparison of its symmetric
+    and general matrix wrappers): D^2 of the converged density matrix by the
+    symmetric square (upper output blocks only) and by the two-operand product
+    D D + D D with c = 1/2, which performs the block multiplications of a
+    general product (every output block of both triangles, as a general
+    wrapper would); wall time of each call after one untimed call."""
+    import torch
+
+    D = sp2.density(F, no, lmin, lmax, hub, llb, **opts).D
+    out = {"nnzb_D": D.nnzb, "precision": prec}
+    for name, fn in (("symmetric_square", lambda: sp2.square_step(D, 0.0, 0.0, 1.0, prec)),
+                     ("general_product", lambda: sp2.pair_product(D, D, sign=1, c=0.5, precision=prec))):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r, sums = fn()
+        torch.cuda.synchronize()
+        out[name + "_s"] = time.perf_counter() - t0
+        out[name + "_tflop"] = (sums[3] if len(sums) == 4 else sums[1]) / 1e12
+        out[name + "_result"] = r
+    a, b = out.pop("symmetric_square_result"), out.pop("general_product_result")
+    out["max_abs_diff"] = float((a.val - b.val).abs().max()) if a.nnzb == b.nnzb else None
+    out["time_ratio"] = out["general_product_s"] / out["symmetric_square_s"]
+    log(f"storage: symmetric {out['symmetric_square_s']:.3f} s ({out['symmetric_square_tflop']:.1f} TF), general "
+        f"{out['general_product_s']:.3f} s ({out['general_product_tflop']:.1f} TF), ratio {out['time_ratio']:.2f}, "
+        f"max |diff| {out['max_abs_diff']}")
+    return out
+
+
 def norm_study(sp2, sizes, half_bw=300, coarse=(128, 512)):
     """The paper's norm comparison (section "Upper bounds for the spectral
     norm"): symmetric banded matrices with entries U(0, 1e-3) and bandwidth
@@ -280,6 +310,9 @@ def main():
     ap.add_argument("--norms", default=None,
                     help="instead of the expansion benchmark: the norm comparison (spectral vs Frobenius vs "
                          "Frob-Inf) on banded and permuted matrices of these sizes, e.g. 1024,2048,4096")
+    ap.add_argument("--storage", action="store_true",
+                    help="instead of the expansion benchmark: the symmetric square of the converged D against the "
+                         "same product done with a general product's block multiplications")
     ap.add_argument("--n-max-cap", type=int, default=None,
                     help="stop after this many iterations (a capped run of a workload too long for one call)")
     ap.add_argument("--bounds", default=None,
@@ -330,6 +363,11 @@ def main():
         torch.cuda.synchronize()
         log(f"calibration copy: {nb} bytes read, {nb} bytes written")
         del src, dst
+
+    if args.storage:
+        res = storage_bench(sp2, F, no, lmin, lmax, hub, llb, opts, args.precision or "fp64")
+        print(json.dumps({"storage": res, "workload": f"lattice {L}^3 x 4, N={info['n']}, tau={tau}"}), flush=True)
+        return
 
     if args.adjoint:
         res = adjoint_bench(sp2, F, Fh, no, lmin, lmax, hub, llb, opts, args.adjoint_runs.split(","))
