@@ -206,7 +206,8 @@ struct TileArgs {
   const int32_t *gidxmap;
   int nbr, W;
   const int32_t *oidx;     // nbr x nbr: pattern position of output block (I, J), or -1
-  const int32_t *tiles;    // ntiles pairs (TI, TJ), TI <= TJ in units of 2 blocks
+  const int32_t *tiles;    // ntiles pairs (TI, TJ), TI <= TJ in units of tb blocks
+  int tb = 2;              // tile edge in blocks: 2 (every kernel) or 4 (BF16x3, dense patterns)
   int64_t ntiles;
   int64_t xcd_chunk;       // tiles per XCD: workgroup b runs tile (b % 8) * xcd_chunk + b / 8
   void *opool;             // output block at its pattern position
@@ -215,7 +216,7 @@ struct TileArgs {
   int64_t n;
   double *parts;           // by pattern position, NPART each
 };
-int64_t build_tiles(Ctx &c, const int32_t *oidx, int nbr, Buf &tiles);
+int64_t build_tiles(Ctx &c, const int32_t *oidx, int nbr, Buf &tiles, int tb = 2);
 void launch_square_tile(Ctx &c, int mode, const TileArgs &a);
 void launch_square_tile_bf16x3(Ctx &c, const TileArgs &a);  // kernels_bf16x3.hip
 // split the stored blocks of an FP32 pool into bf16 hi/lo images of the block

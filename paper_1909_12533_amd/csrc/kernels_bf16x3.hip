@@ -203,7 +203,7 @@ __global__ __launch_bounds__(TPB, 2) void k_square_tile_bf16x3(TileArgs a) {
           fbl[n] = *reinterpret_cast<const u32x4 *>(bl + o);
         }
         // per A tile: the four accumulators of its row take lo*hi, then
-        // hi*lo, then hi*hi (four independent MFMAs between dependent ones)
+        // hi*hi, then hi*lo (four independent MFMAs between dependent ones)
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
           const int o = (16 * m + l16) * LDH + ks + 8 * g;
@@ -212,9 +212,9 @@ __global__ __launch_bounds__(TPB, 2) void k_square_tile_bf16x3(TileArgs a) {
 #pragma unroll
           for (int n = 0; n < 4; ++n) acc[m][n] = mfma_bf16(fal, fbh[n], acc[m][n]);
 #pragma unroll
-          for (int n = 0; n < 4; ++n) acc[m][n] = mfma_bf16(fah, fbl[n], acc[m][n]);
-#pragma unroll
           for (int n = 0; n < 4; ++n) acc[m][n] = mfma_bf16(fah, fbh[n], acc[m][n]);
+#pragma unroll
+          for (int n = 0; n < 4; ++n) acc[m][n] = mfma_bf16(fah, fbl[n], acc[m][n]);
         }
       }
       ++nk;
@@ -227,6 +227,210 @@ __global__ __launch_bounds__(TPB, 2) void k_square_tile_bf16x3(TileArgs a) {
   if (pos < 0) return;
   // f32 16 x 16 accumulator layout: element v of lane group g is row 4 g + v
   square_epilogue<float, TO>(acc, a, I, J, pos, nk, [](int gg, int q) { return 4 * gg + q; });
+}
+
+// ---------------------------------------------------------------------------
+// 4 x 4 tiles of output blocks, for dense patterns.  The k_square_tile_bf16x3
+// above is bound by operand traffic: each staged block serves two products.
+// Here the workgroup stages the images of four left operand blocks (rows
+// I0..I0+3 at K) and four right ones (columns J0..J0+3) for 16 products, half
+// the traffic per product.  The images go straight from global memory to LDS
+// (global_load_lds_dwordx4), one 32-deep k half at a time, double-buffered:
+// k half 0 of every K lives in stage S0 and k half 1 in S1, so the load of
+// the next half overlaps the MFMAs of the current one, and no registers are
+// spent on staging.  8 waves, two per SIMD; wave w multiplies row block
+// I0 + w / 2 by column blocks J0 + 2 (w % 2) + b, b = 0, 1 (2 x 16
+// accumulator tiles).  Accumulation order per output element is that of
+// k_square_tile_bf16x3 (K ascending; k half 0 then 1; lo*hi, hi*hi, hi*lo),
+// so the two kernels give bit-identical results.
+//
+// LDS layout of one operand plane in a stage: 64 rows x 32 bf16 (64 bytes,
+// four 16-byte chunks); logical chunk g of row R sits at chunk g ^ swz(R),
+// swz(R) = bit2(R) | (bit1(R) ^ bit3(R)) << 1, which makes the 16-byte
+// fragment reads of 16 (or 8) consecutive rows hit distinct banks.  A wave's
+// load instruction writes 1 KB contiguously (lane l at byte 16 l), i.e.
+// 16 rows; each lane fetches the global chunk that belongs at its slot.
+
+__device__ inline int swz(int R) { return ((R >> 2) & 1) | ((((R >> 1) ^ (R >> 3)) & 1) << 1); }
+
+constexpr int HPLANE = 64 * 32;  // bf16 per operand plane and k half
+
+// a staged K, as one wave sees it: the slots (-1: absent) and sign masks of
+// the operand blocks it multiplies (row ia, columns jp and jp + 1), and the
+// slot of the operand it loads into LDS (operand w: A0..A3 = rows I0..I0+3 at
+// K, B0..B3 = columns J0..J0+3)
+struct Stage4 {
+  int K, kp;
+  int32_t sa, sb0, sb1, sd;
+  uint32_t ga, gb0, gb1;
+};
+
+template <typename TO, bool GEN>
+__global__ __launch_bounds__(512, 2) void k_square_tile4_bf16x3(TileArgs a) {
+  __shared__ __align__(16) uint16_t S0[8][2][HPLANE];  // k half 0 of the current K
+  __shared__ __align__(16) uint16_t S1[8][2][HPLANE];  // k half 1
+  const int64_t t = xcd_tile(a);
+  if (t < 0) return;
+  const int nbr = a.nbr, W = a.W;
+  const int I0 = 4 * __builtin_amdgcn_readfirstlane(a.tiles[2 * t]);
+  const int J0 = 4 * __builtin_amdgcn_readfirstlane(a.tiles[2 * t + 1]);
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+  const int ia = wave >> 1, jp = 2 * (wave & 1);
+  const int I = I0 + ia, Jb0 = J0 + jp, Jb1 = J0 + jp + 1;
+  int32_t pos0 = -1, pos1 = -1;
+  if (I < nbr && Jb0 < nbr && I <= Jb0) pos0 = __builtin_amdgcn_readfirstlane(a.oidx[(int64_t)I * nbr + Jb0]);
+  if (I < nbr && Jb1 < nbr && I <= Jb1) pos1 = __builtin_amdgcn_readfirstlane(a.oidx[(int64_t)I * nbr + Jb1]);
+  const u32x4 *xq = static_cast<const u32x4 *>(a.xpack);
+  const u32x4 *yq = static_cast<const u32x4 *>(GEN ? a.ypack : a.xpack);
+
+  f4 acc0[4][4], acc1[4][4];
+#pragma unroll
+  for (int m = 0; m < 4; ++m)
+#pragma unroll
+    for (int n = 0; n < 4; ++n) {
+      acc0[m][n] = f4{0, 0, 0, 0};
+      acc1[m][n] = f4{0, 0, 0, 0};
+    }
+
+  // K over the union of the 16 blocks' K sets (second pass: operands
+  // swapped); the right operand's slots are read along row J of the symmetric
+  // slot map.  Once exhausted the scan keeps returning false.
+  const uint32_t *lbits = a.bits, *rbits = GEN ? a.ybits : a.bits;
+  int wi = -1, pass = 0;
+  uint32_t mask = 0u;
+  auto next_k = [&](Stage4 &q) -> bool {
+    while (mask == 0u) {
+      ++wi;
+      if (wi >= W) {
+        if (!GEN || pass + 1 >= a.npass) {
+          wi = W;
+          return false;
+        }
+        ++pass;
+        wi = -1;
+        lbits = a.ybits;
+        rbits = a.bits;
+        continue;
+      }
+      uint32_t ra = 0u, rb = 0u;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        if (I0 + r < nbr) ra |= lbits[(int64_t)(I0 + r) * W + wi];
+        if (J0 + r < nbr) rb |= rbits[(int64_t)(J0 + r) * W + wi];
+      }
+      mask = (uint32_t)__builtin_amdgcn_readfirstlane((int)(ra & rb));
+    }
+    const int K = wi * 32 + __builtin_ctz(mask);
+    mask &= mask - 1u;
+    q.K = K;
+    q.kp = pass;
+    const int32_t *li = (GEN && pass) ? a.yidxmap : a.idxmap;
+    const int32_t *ri = GEN ? (pass ? a.idxmap : a.yidxmap) : a.idxmap;
+    const bool la = GEN && (pass ? a.yanti : a.xanti), rn = GEN && (pass ? a.xanti : a.yanti);
+    const bool ng = GEN && pass && a.neg2;
+    constexpr uint32_t SGN2 = 0x80008000u;
+    q.sa = I < nbr ? __builtin_amdgcn_readfirstlane(li[(int64_t)I * nbr + K]) : -1;
+    q.sb0 = Jb0 < nbr ? __builtin_amdgcn_readfirstlane(ri[(int64_t)Jb0 * nbr + K]) : -1;
+    q.sb1 = Jb1 < nbr ? __builtin_amdgcn_readfirstlane(ri[(int64_t)Jb1 * nbr + K]) : -1;
+    q.ga = ((la && I > K) != ng) ? SGN2 : 0u;
+    q.gb0 = (rn && K > Jb0) ? SGN2 : 0u;
+    q.gb1 = (rn && K > Jb1) ? SGN2 : 0u;
+    const int Rd = wave < 4 ? I0 + wave : J0 + wave - 4;  // the operand this wave loads
+    q.sd = Rd < nbr ? __builtin_amdgcn_readfirstlane((wave < 4 ? li : ri)[(int64_t)Rd * nbr + K]) : -1;
+    return true;
+  };
+
+  // k half kh of the 8 operand images of q into stage st: 64 load
+  // instructions of 1 KB (operand o, plane pl, 16-row group rg); wave w issues
+  // the 8 of operand w.  Lane l fills row 16 rg + l / 4, chunk l % 4 of the
+  // group with the global chunk of logical k chunk (l % 4) ^ swz(row) (swz
+  // depends on row % 16 only).
+  const uint32_t loff = (uint32_t)(((lane >> 2) * 8 + ((lane & 3) ^ swz(lane >> 2))) * 16);
+  auto dma = [&](const Stage4 &q, int kh, uint16_t (*st)[2][HPLANE]) {
+    const u32x4 *base = ((wave < 4) == !(GEN && q.kp)) ? xq : yq;
+    const int32_t so = q.sd > 0 ? q.sd : 0;  // absent: slot 0, never multiplied
+    const bool nimg = wave < 4 ? (I0 + wave <= q.K) : (q.K > J0 + wave - 4);
+    const char *img =
+        reinterpret_cast<const char *>(base + (int64_t)so * BLK_Q + (nimg ? 0 : IMG_Q) + kh * 4);
+#pragma unroll
+    for (int pl = 0; pl < 2; ++pl)
+#pragma unroll
+      for (int rg = 0; rg < 4; ++rg)
+        __builtin_amdgcn_global_load_lds(img + pl * 8192 + rg * 2048 + loff, &st[wave][pl][rg * 16 * 32], 16, 0,
+                                         0);
+  };
+
+  // one k half: per output block the 16 accumulator tiles take lo*hi, then
+  // hi*hi, then hi*lo; four A and four B fragments live at a time
+  const int l16 = lane & 15, g = lane >> 4;
+  const int foff = l16 * 32 + ((g ^ swz(l16)) << 3);  // fragment of tile t at foff + 512 t
+  int nk0 = 0, nk1 = 0;
+  auto compute = [&](const Stage4 &q, uint16_t (*st)[2][HPLANE]) {
+    const bool act0 = pos0 >= 0 && q.sa >= 0 && q.sb0 >= 0;
+    const bool act1 = pos1 >= 0 && q.sa >= 0 && q.sb1 >= 0;
+    nk0 += act0 ? 1 : 0;
+    nk1 += act1 ? 1 : 0;
+    if (!act0 && !act1) return;
+    const uint16_t *ah = st[ia][0], *al = st[ia][1];
+    const uint16_t *b0h = st[4 + jp][0], *b0l = st[4 + jp][1], *b1h = st[5 + jp][0], *b1l = st[5 + jp][1];
+    u32x4 fa[4], fb[4];
+    auto ld = [&](u32x4(&f)[4], const uint16_t *pl, uint32_t sg) {
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        f[t] = *reinterpret_cast<const u32x4 *>(pl + foff + 512 * t);
+        if (GEN) f[t] ^= u32x4{sg, sg, sg, sg};
+      }
+    };
+    auto mm = [&](f4(&ac)[4][4]) {
+#pragma unroll
+      for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int n = 0; n < 4; ++n) ac[m][n] = mfma_bf16(fa[m], fb[n], ac[m][n]);
+    };
+    ld(fa, al, q.ga);
+    if (act0) {
+      ld(fb, b0h, q.gb0);
+      mm(acc0);  // block 0: lo*hi
+    }
+    if (act1) {
+      ld(fb, b1h, q.gb1);
+      mm(acc1);  // block 1: lo*hi
+    }
+    ld(fa, ah, q.ga);
+    if (act1) mm(acc1);  // block 1: hi*hi (fb still holds its hi plane)
+    if (act0) {
+      ld(fb, b0h, q.gb0);
+      mm(acc0);  // block 0: hi*hi
+      ld(fb, b0l, q.gb0);
+      mm(acc0);  // block 0: hi*lo
+    }
+    if (act1) {
+      ld(fb, b1l, q.gb1);
+      mm(acc1);  // block 1: hi*lo
+    }
+  };
+
+  Stage4 q, qn;
+  if (next_k(q)) {
+    dma(q, 0, S0);
+    while (true) {
+      __syncthreads();  // k half 0 of K in S0 (every wave waited for its loads); S1 free
+      dma(q, 1, S1);
+      compute(q, S0);
+      const bool more = next_k(qn);
+      __syncthreads();  // k half 1 in S1; S0 free
+      if (more) dma(qn, 0, S0);
+      compute(q, S1);
+      if (!more) break;
+      q = qn;
+    }
+  }
+  // f32 16 x 16 accumulator layout: element v of lane group g is row 4 g + v;
+  // nk counted both k halves of every K
+  const auto rowf = [](int gg, int qq) { return 4 * gg + qq; };
+  if (pos0 >= 0) square_epilogue<float, TO>(acc0, a, I, Jb0, pos0, nk0 / 2, rowf);
+  if (pos1 >= 0) square_epilogue<float, TO>(acc1, a, I, Jb1, pos1, nk1 / 2, rowf);
 }
 
 }  // namespace
@@ -243,6 +447,22 @@ void launch_square_tile_bf16x3(Ctx &c, const TileArgs &a) {
   const bool gen = a.ypool != a.xpool || a.npass != 1 || a.xanti || a.yanti;
   if (!a.xpack || (gen && !a.ypack)) fail(SP2_ERR_INVALID_ARG, "BF16x3 square needs packed operands");
   const unsigned g = (unsigned)(8 * a.xcd_chunk);
+  if (a.tb == 4) {
+    if (a.oprec == P32) {
+      if (gen)
+        k_square_tile4_bf16x3<float, true><<<g, 512, 0, c.stream>>>(a);
+      else
+        k_square_tile4_bf16x3<float, false><<<g, 512, 0, c.stream>>>(a);
+    } else {
+      if (gen)
+        k_square_tile4_bf16x3<double, true><<<g, 512, 0, c.stream>>>(a);
+      else
+        k_square_tile4_bf16x3<double, false><<<g, 512, 0, c.stream>>>(a);
+    }
+    SP2_LAUNCH_CHECK();
+    return;
+  }
+  if (a.tb != 2) fail(SP2_ERR_INVALID_ARG, "BF16x3 square: tile edge must be 2 or 4 blocks");
   if (a.oprec == P32) {
     if (gen)
       k_square_tile_bf16x3<float, true><<<g, TPB, 0, c.stream>>>(a);

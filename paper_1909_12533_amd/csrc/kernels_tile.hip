@@ -284,16 +284,16 @@ __device__ inline bool tile_of(int64_t id, int ntr, int nst, int &TI, int &TJ) {
   return TI < ntr && TJ < ntr && TI <= TJ;
 }
 
-// flags of 2 x 2 output tiles holding at least one output block
-__global__ void k_tile_flags(const int32_t *oidx, int nbr, int ntr, int nst, int64_t nid, int64_t *flag) {
+// flags of tb x tb output tiles holding at least one output block
+__global__ void k_tile_flags(const int32_t *oidx, int nbr, int tb, int ntr, int nst, int64_t nid, int64_t *flag) {
   const int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (id >= nid) return;
   int TI, TJ;
   int64_t f = 0;
   if (tile_of(id, ntr, nst, TI, TJ)) {
-    for (int a = 0; a < 2; ++a)
-      for (int b = 0; b < 2; ++b) {
-        const int I = 2 * TI + a, J = 2 * TJ + b;
+    for (int a = 0; a < tb; ++a)
+      for (int b = 0; b < tb; ++b) {
+        const int I = tb * TI + a, J = tb * TJ + b;
         if (I < nbr && J < nbr && I <= J && oidx[(int64_t)I * nbr + J] >= 0) f = 1;
       }
   }
@@ -312,12 +312,14 @@ __global__ void k_tile_write(const int64_t *flag, const int64_t *pos, int ntr, i
 
 }  // namespace
 
-int64_t build_tiles(Ctx &c, const int32_t *oidx, int nbr, Buf &tiles) {
-  const int ntr = (nbr + 1) / 2;
+int64_t build_tiles(Ctx &c, const int32_t *oidx, int nbr, Buf &tiles, int tb) {
+  if (tb != 2 && tb != 4) fail(SP2_ERR_INVALID_ARG, "tile edge must be 2 or 4 blocks");
+  const int ntr = (nbr + tb - 1) / tb;
   const int nst = (ntr + ST - 1) / ST;
   const int64_t nid = (int64_t)nst * nst * ST * ST;
   Buf flag = c.alloc(sizeof(int64_t) * nid), pos = c.alloc(sizeof(int64_t) * (nid + 1));
-  k_tile_flags<<<(unsigned)((nid + TPB - 1) / TPB), TPB, 0, c.stream>>>(oidx, nbr, ntr, nst, nid, flag.as<int64_t>());
+  k_tile_flags<<<(unsigned)((nid + TPB - 1) / TPB), TPB, 0, c.stream>>>(oidx, nbr, tb, ntr, nst, nid,
+                                                                        flag.as<int64_t>());
   SP2_LAUNCH_CHECK();
   scan_exclusive_i64(c, flag.as<int64_t>(), pos.as<int64_t>(), nid);
   int64_t nt = 0;
@@ -331,6 +333,7 @@ int64_t build_tiles(Ctx &c, const int32_t *oidx, int nbr, Buf &tiles) {
 
 void launch_square_tile(Ctx &c, int mode, const TileArgs &a) {
   if (a.ntiles <= 0) return;
+  if (a.tb != 2 && mode != M_BF16X3) fail(SP2_ERR_INVALID_ARG, "4 x 4 tiles are for the BF16x3 square only");
   const bool gen = a.ypool != a.xpool || a.npass != 1 || a.xanti || a.yanti;
   if (gen && !(a.ypool && a.yidxmap && a.ybits && (a.npass == 1 || a.npass == 2)))
     fail(SP2_ERR_INVALID_ARG, "tiled product: incomplete second operand");

@@ -253,6 +253,20 @@ Buf pack_operand(Ctx &c, const DMat &X, int mode) {
   return b;
 }
 
+// Tile edge of a BF16x3 product: 4 x 4 output tiles (k_square_tile4_bf16x3,
+// half the operand traffic per block product) once the output pattern holds
+// at least half of the upper blocks, else 2 x 2 (the 4 x 4 K scan runs over
+// the union of 8 block rows, wasteful on sparse patterns).  The environment
+// variable SP2_BF16X3_TILE = 2 or 4 forces one of them.
+int tile_edge(int mode, int64_t nout, int nbr) {
+  if (mode != M_BF16X3) return 2;
+  if (const char *e = std::getenv("SP2_BF16X3_TILE")) {
+    if (e[0] == '2') return 2;
+    if (e[0] == '4') return 4;
+  }
+  return (double)nout >= 0.25 * (double)nbr * (double)(nbr + 1) ? 4 : 2;
+}
+
 struct SquareOut {
   DMat next;      // X_{i+1} (or S when fused == false) on the square's pattern
   Buf parts;      // nout x NPART
@@ -278,11 +292,13 @@ SquareOut square_step(Ctx &c, const DMat &X, const Maps &m, int mode, int oprec,
   const int64_t nout = r.next.pat.nnzb;
   r.next.pool = new_pool(c, oprec, nout);
   r.parts = c.alloc(sizeof(double) * NPART * (size_t)(nout > 0 ? nout : 1));
-  // 2 x 2 output tiles over the square's pattern
+  // output tiles over the square's pattern
   Maps om = build_maps(c, r.next.pat, false);
   Buf tiles;
-  const int64_t ntiles = build_tiles(c, om.idxmap.as<int32_t>(), X.pat.nbr, tiles);
+  const int tb = tile_edge(mode, nout, X.pat.nbr);
+  const int64_t ntiles = build_tiles(c, om.idxmap.as<int32_t>(), X.pat.nbr, tiles, tb);
   TileArgs ta;
+  ta.tb = tb;
   ta.xpool = X.pool->vals.p;
   ta.xprec = X.pool->prec;
   ta.idxmap = m.idxmap.as<int32_t>();
@@ -353,8 +369,10 @@ SquareOut pair_product(Ctx &c, const DMat &X, const Maps &mx, const DMat &Y, con
   r.parts = c.alloc(sizeof(double) * NPART * (size_t)(nout > 0 ? nout : 1));
   Maps om = build_maps(c, r.next.pat, false);
   Buf tiles;
-  const int64_t ntiles = build_tiles(c, om.idxmap.as<int32_t>(), X.pat.nbr, tiles);
+  const int tb = tile_edge(po.mode, nout, X.pat.nbr);
+  const int64_t ntiles = build_tiles(c, om.idxmap.as<int32_t>(), X.pat.nbr, tiles, tb);
   TileArgs ta;
+  ta.tb = tb;
   ta.xpool = X.pool->vals.p;
   ta.xprec = X.pool->prec;
   ta.idxmap = mx.idxmap.as<int32_t>();
