@@ -255,16 +255,17 @@ Buf pack_operand(Ctx &c, const DMat &X, int mode) {
 
 // Tile edge of a BF16x3 product: 4 x 4 output tiles (k_square_tile4_bf16x3,
 // half the operand traffic per block product) once the output pattern holds
-// at least half of the upper blocks, else 2 x 2 (the 4 x 4 K scan runs over
-// the union of 8 block rows, wasteful on sparse patterns).  The environment
-// variable SP2_BF16X3_TILE = 2 or 4 forces one of them.
+// at least 35% of the upper blocks, else 2 x 2 (the 4 x 4 K scan runs over the
+// union of 8 block rows, wasteful on sparse patterns; on the C1 expansion the
+// two kernels break even near 35-40%).  The environment variable
+// SP2_BF16X3_TILE = 2 or 4 forces one of them.
 int tile_edge(int mode, int64_t nout, int nbr) {
   if (mode != M_BF16X3) return 2;
   if (const char *e = std::getenv("SP2_BF16X3_TILE")) {
     if (e[0] == '2') return 2;
     if (e[0] == '4') return 4;
   }
-  return (double)nout >= 0.25 * (double)nbr * (double)(nbr + 1) ? 4 : 2;
+  return (double)nout >= 0.35 * 0.5 * (double)nbr * (double)(nbr + 1) ? 4 : 2;
 }
 
 struct SquareOut {
