@@ -69,7 +69,10 @@ extern "C" {
 /* precision of the bulk squares */
 #define SP2_PREC_FP64 0   /* every square in FP64 MFMA */
 #define SP2_PREC_FP32 1   /* FP32 MFMA squares (FP32 storage) until e_i < switch_tol, then FP64 */
-#define SP2_PREC_BF16X3 2 /* BF16 hi/lo split MFMA (hi*hi + hi*lo + lo*hi, FP32 accumulate), then FP64 */
+#define SP2_PREC_BF16X3 2 /* BF16 hi/lo split MFMA (hi*hi + hi*lo + lo*hi, FP32 accumulate), then FP64.
+                             Products whose output pattern holds >= 35% of the upper blocks run on
+                             4 x 4-block tiles, sparser ones on 2 x 2 (bit-identical results); the
+                             environment variable SP2_BF16X3_TILE = 2 or 4 forces one of them. */
 
 /* truncation norm (section "Upper bounds for the spectral norm") */
 #define SP2_TRUNC_NONE 0
