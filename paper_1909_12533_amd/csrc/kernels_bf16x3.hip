@@ -362,7 +362,9 @@ __global__ __launch_bounds__(512, 2) void k_square_tile4_bf16x3(TileArgs a) {
   };
 
   // one k half: per output block the 16 accumulator tiles take lo*hi, then
-  // hi*hi, then hi*lo; four A and four B fragments live at a time
+  // hi*hi, then hi*lo.  Six fragment groups (A lo, B0 hi, B1 hi, A hi, B1 lo,
+  // B0 lo) in two A and two B register sets; each group is read from LDS one
+  // 16-MFMA step before its first use, so the reads run under the MFMAs.
   const int l16 = lane & 15, g = lane >> 4;
   const int foff = l16 * 32 + ((g ^ swz(l16)) << 3);  // fragment of tile t at foff + 512 t
   int nk0 = 0, nk1 = 0;
@@ -374,7 +376,7 @@ __global__ __launch_bounds__(512, 2) void k_square_tile4_bf16x3(TileArgs a) {
     if (!act0 && !act1) return;
     const uint16_t *ah = st[ia][0], *al = st[ia][1];
     const uint16_t *b0h = st[4 + jp][0], *b0l = st[4 + jp][1], *b1h = st[5 + jp][0], *b1l = st[5 + jp][1];
-    u32x4 fa[4], fb[4];
+    u32x4 fa0[4], fa1[4], fb0[4], fb1[4];
     auto ld = [&](u32x4(&f)[4], const uint16_t *pl, uint32_t sg) {
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
@@ -382,33 +384,28 @@ __global__ __launch_bounds__(512, 2) void k_square_tile4_bf16x3(TileArgs a) {
         if (GEN) f[t] ^= u32x4{sg, sg, sg, sg};
       }
     };
-    auto mm = [&](f4(&ac)[4][4]) {
+    auto mm = [&](f4(&ac)[4][4], const u32x4(&fa)[4], const u32x4(&fb)[4]) {
 #pragma unroll
       for (int m = 0; m < 4; ++m)
 #pragma unroll
         for (int n = 0; n < 4; ++n) ac[m][n] = mfma_bf16(fa[m], fb[n], ac[m][n]);
     };
-    ld(fa, al, q.ga);
-    if (act0) {
-      ld(fb, b0h, q.gb0);
-      mm(acc0);  // block 0: lo*hi
-    }
+    ld(fa0, al, q.ga);
+    if (act0) ld(fb0, b0h, q.gb0);
+    if (act1) ld(fb1, b1h, q.gb1);
+    if (act0) mm(acc0, fa0, fb0);  // block 0: lo*hi
+    ld(fa1, ah, q.ga);
+    if (act1) mm(acc1, fa0, fb1);  // block 1: lo*hi
     if (act1) {
-      ld(fb, b1h, q.gb1);
-      mm(acc1);  // block 1: lo*hi
+      mm(acc1, fa1, fb1);  // block 1: hi*hi
+      ld(fb1, b1l, q.gb1);
     }
-    ld(fa, ah, q.ga);
-    if (act1) mm(acc1);  // block 1: hi*hi (fb still holds its hi plane)
     if (act0) {
-      ld(fb, b0h, q.gb0);
-      mm(acc0);  // block 0: hi*hi
-      ld(fb, b0l, q.gb0);
-      mm(acc0);  // block 0: hi*lo
+      mm(acc0, fa1, fb0);  // block 0: hi*hi
+      ld(fb0, b0l, q.gb0);
     }
-    if (act1) {
-      ld(fb, b1l, q.gb1);
-      mm(acc1);  // block 1: hi*lo
-    }
+    if (act1) mm(acc1, fa1, fb1);  // block 1: hi*lo
+    if (act0) mm(acc0, fa1, fb0);  // block 0: hi*lo
   };
 
   Stage4 q, qn;
