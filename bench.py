@@ -72,28 +72,34 @@ def cpu_baseline(L=12, tau=1e-6):
     }
 
 
-KERNEL_SOURCES = ["paper_1909_12533_amd/csrc/kernels_tile.hip", "paper_1909_12533_amd/csrc/mfma.h"]
+# dominant kernel of a run in each bulk precision, and the sources it is built from
+KERNELS = {
+    "fp64": ("k_square_f64_lds", ["paper_1909_12533_amd/csrc/kernels_f64.hip", "paper_1909_12533_amd/csrc/mfma.h"]),
+    "fp32": ("k_square_tile", ["paper_1909_12533_amd/csrc/kernels_tile.hip", "paper_1909_12533_amd/csrc/mfma.h"]),
+    "bf16x3": ("k_square_tile4_bf16x3", ["paper_1909_12533_amd/csrc/kernels_bf16x3.hip",
+                                          "paper_1909_12533_amd/csrc/mfma.h"]),
+}
 
 
-def kernel_source_hash():
+def kernel_source_hash(prec="fp64"):
     import hashlib
 
     h = hashlib.sha256()
     root = os.path.dirname(os.path.abspath(__file__))
-    for f in KERNEL_SOURCES:
+    for f in KERNELS[prec][1]:
         with open(os.path.join(root, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
 
 
 def traffic_per_launch(prec, L):
-    """HBM bytes per launch of the FP64 square from the committed rocprofv3
-    FETCH_SIZE / WRITE_SIZE summary of this workload, each counter scaled by
-    what it read for a 1 GiB device copy in the same run; None when there is no
-    summary for this kernel and workload or the kernel sources changed since the
-    counters were taken."""
+    """HBM bytes per launch of the run's dominant square kernel from the
+    committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary of this workload, each
+    counter scaled by what it read for a 1 GiB device copy in the same run;
+    None when there is no summary for this kernel and workload or the kernel
+    sources changed since the counters were taken."""
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
-                        f"k_square_tile_{prec}_lattice{L}_pmc.txt")
+                        f"{KERNELS[prec][0]}_{prec}_lattice{L}_pmc.txt")
     if not os.path.exists(path):
         return None
     kv = {}
@@ -102,7 +108,7 @@ def traffic_per_launch(prec, L):
             parts = line.split()
             if len(parts) == 2 and not line.startswith("#"):
                 kv[parts[0]] = parts[1]
-    if kv.get("source_sha256") != kernel_source_hash():
+    if kv.get("source_sha256") != kernel_source_hash(prec):
         return None
     kib = float(kv["fetch_kib_per_launch"]) * float(kv["fetch_factor"]) + \
         float(kv["write_kib_per_launch"]) * float(kv["write_factor"])
@@ -485,7 +491,7 @@ def main():
                    "lumo_est": None if math.isnan(res.lumo_est) else res.lumo_est, **mixed},
         "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK[prec], "unit": "TFLOP/s",
                      "frac": round(achieved / PEAK[prec], 4), "traffic": traffic_per_launch(prec, L),
-                     "kernel": "k_square_tile (MFMA block-sparse symmetric square + fused epilogue)"},
+                     "kernel": f"{KERNELS[prec][0]} (MFMA block-sparse symmetric square + fused epilogue)"},
     }
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)...")

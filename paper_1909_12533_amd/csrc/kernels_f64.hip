@@ -1,0 +1,253 @@
+// FP64 square with operands loaded straight to LDS (the symmetric square of
+// Algorithm 2 in FP64, the method's reference arithmetic).
+//
+// One workgroup of four waves per 2 x 2 tile of output blocks; wave w owns the
+// whole 64 x 64 block (I0 + w / 2, J0 + w % 2) in 4 x 4 MFMA accumulator tiles.
+// K runs ascending over the union of the tile's K sets and each K is taken in
+// four 16-deep k quarters, so every output element accumulates in the same
+// order as in k_square_tile<double, double, false, 8> (K ascending, 16-deep k
+// chunks in order, k = 4 g + s within an MFMA): the two give bit-identical
+// results, the block sums included (added over rows 0..31 and 32..63 in that
+// order).
+//
+// Staging: each quarter of the four operand blocks (A0, A1, B0, B1; 8 KB
+// each) is loaded by global_load_lds_dwordx4 straight into LDS, wave w
+// loading operand w; quarters alternate between two stages (64 KB in all, so
+// two workgroups share a CU and one computes while the other waits at a
+// barrier), and the load of the next quarter runs under the MFMAs of the
+// current one.  The slot lookups of the next K are issued before the MFMAs of
+// a quarter and consumed after them.
+//
+// A staged quarter of a stored 64 x 64 block is either its 16 columns k, as
+// [64 rows][16 k] (128-byte rows, "kcol": the operand is used untransposed
+// along k) or its 16 rows k, as [16 k][64 columns] (512-byte rows, "krow":
+// used transposed).  The 16-byte chunks of each row are XOR-swizzled so that
+// the fragment reads of 16 lanes hit distinct banks:
+//   kcol: chunk c of row r at position c ^ ((r >> 1) & 7);
+//   krow: chunk c of k-row kr at position c ^ (8 * ((kr >> 2) & 1)).
+// One load instruction writes 1 KB of LDS contiguously (lane l at byte 16 l):
+// 8 kcol rows or 2 krow rows; each lane fetches the global chunk that belongs
+// at its position.
+#include "mfma.h"
+
+namespace sp2 {
+
+namespace {
+
+using namespace dev;
+
+
+constexpr int QS = 64 * 16;  // doubles per operand quarter-slice (8 KB)
+
+// quarter slices: kcol [64 rows][16 k] (128-byte rows, chunk c of row r at
+// position c ^ ((r >> 1) & 7)); krow [16 k][64 columns] (512-byte rows, chunk
+// c of k-row kr at position c ^ (8 ((kr >> 2) & 1)))
+__device__ __forceinline__ int qcol_pos(int r, int c) { return c ^ ((r >> 1) & 7); }
+__device__ __forceinline__ int qrow_pos(int kr, int c) { return c ^ (((kr >> 2) & 1) << 3); }
+
+// One quarter of MFMAs for the wave's 64 x 64 block: 4 x 4 accumulator tiles,
+// k = 4 g + s (lane group g = lane / 16, MFMA s = 0..3), fragments read in
+// pairs s = 2 sp, 2 sp + 1.  The orientation of each operand is a run-time
+// choice of per-lane offsets (one code path: the accumulators stay in place);
+// a kcol pair is the two halves of one 16-byte chunk (second at +8), a krow
+// pair two k-rows (second at +512).  Every read is one byte offset from the
+// stage array: the compiler tells reads of one stage from the loads still
+// landing in the other only for addresses it can trace to the array in a few
+// steps.
+__device__ __forceinline__ int frag_off(bool kcol, int r, int k) {
+  return kcol ? 16 * (r * 8 + qcol_pos(r, k >> 1)) : 8 * (k * 64 + qrow_pos(k, r >> 1) * 2 + (r & 1));
+}
+
+__device__ __forceinline__ void mma_quarter(d4 (&acc)[4][4], const char *st, int oa, int ob, bool ka, bool kb,
+                                            int lane) {
+  const int l16 = lane & 15;
+  const int da = ka ? 8 : 512, db = kb ? 8 : 512;
+#pragma unroll
+  for (int sp = 0; sp < 2; ++sp) {
+    const int k = 4 * (lane >> 4) + 2 * sp;
+    double fa[4][2], fb[4][2];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const int o = oa + frag_off(ka, 16 * m + l16, k);
+      fa[m][0] = *reinterpret_cast<const double *>(st + o);
+      fa[m][1] = *reinterpret_cast<const double *>(st + o + da);
+    }
+#pragma unroll
+    for (int n = 0; n < 4; ++n) {
+      const int o = ob + frag_off(kb, 16 * n + l16, k);
+      fb[n][0] = *reinterpret_cast<const double *>(st + o);
+      fb[n][1] = *reinterpret_cast<const double *>(st + o + db);
+    }
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+      for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int n = 0; n < 4; ++n) acc[m][n] = MF<double>::op(fa[m][s], fb[n][s], acc[m][n]);
+  }
+}
+
+__global__ __launch_bounds__(256, 2) void k_square_f64_lds(TileArgs a) {
+  __shared__ __align__(16) double S0[4][QS];  // even quarters: A0, A1, B0, B1
+  __shared__ __align__(16) double S1[4][QS];  // odd quarters
+  const int64_t t = xcd_tile(a);
+  if (t < 0) return;
+  const int nbr = a.nbr, W = a.W;
+  const int I0 = 2 * __builtin_amdgcn_readfirstlane(a.tiles[2 * t]);
+  const int J0 = 2 * __builtin_amdgcn_readfirstlane(a.tiles[2 * t + 1]);
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+  const int ia = wave >> 1, jb = wave & 1;
+  const int I = I0 + ia, J = J0 + jb;
+  const bool has_i1 = I0 + 1 < nbr, has_j1 = J0 + 1 < nbr;
+  int32_t pos = -1;
+  if (I < nbr && J < nbr && I <= J) pos = __builtin_amdgcn_readfirstlane(a.oidx[(int64_t)I * nbr + J]);
+
+  d4 acc[4][4];
+#pragma unroll
+  for (int m = 0; m < 4; ++m)
+#pragma unroll
+    for (int n = 0; n < 4; ++n) acc[m][n] = d4{0, 0, 0, 0};
+
+  // K over the union of the four blocks' K sets; once exhausted it keeps
+  // returning false
+  const uint32_t *bI0 = a.bits + (int64_t)I0 * W, *bI1 = a.bits + (int64_t)(has_i1 ? I0 + 1 : I0) * W;
+  const uint32_t *bJ0 = a.bits + (int64_t)J0 * W, *bJ1 = a.bits + (int64_t)(has_j1 ? J0 + 1 : J0) * W;
+  int wi = -1;
+  uint32_t mask = 0u;
+  // staged K as one wave sees it: the slots of its own A and B blocks, the
+  // slot of the operand it loads (operand w: A0, A1, B0, B1) and the
+  // orientations (kcol) of those three
+  struct StK {
+    int K;
+    int32_t sa, sb, sd;
+    bool ka, kb, kd;
+  };
+  const int Rd = wave < 2 ? I0 + wave : J0 + wave - 2;  // block row of the operand this wave loads
+  // a zero the compiler takes for a per-lane value: the slot loads below then
+  // stay in vector registers (and unwaited) until fin_k
+  int vz = 0;
+  asm volatile("" : "+v"(vz));
+  auto next_k = [&](StK &q) -> bool {
+    while (mask == 0u) {
+      ++wi;
+      if (wi >= W) {
+        wi = W;
+        return false;
+      }
+      const uint32_t ra = bI0[wi] | (has_i1 ? bI1[wi] : 0u);
+      const uint32_t rb = bJ0[wi] | (has_j1 ? bJ1[wi] : 0u);
+      mask = (uint32_t)__builtin_amdgcn_readfirstlane((int)(ra & rb));
+    }
+    const int K = wi * 32 + __builtin_ctz(mask);
+    mask &= mask - 1u;
+    q.K = K;
+    // the slot loads are only issued here; fin_k makes them wave-uniform
+    // after the MFMAs of a quarter, so their latency is hidden (rows past the
+    // last block row read row 0 and are replaced by -1 in fin_k)
+    const int32_t *im = a.idxmap + vz;
+    q.sa = im[(int64_t)(I < nbr ? I : 0) * nbr + K];
+    q.sb = im[(int64_t)(J < nbr ? J : 0) * nbr + K];
+    q.ka = !(I > K);
+    q.kb = K > J;
+    q.sd = im[(int64_t)(Rd < nbr ? Rd : 0) * nbr + K];
+    q.kd = wave < 2 ? !(Rd > K) : (K > Rd);
+    return true;
+  };
+  auto fin_k = [&](StK &q) {
+    q.sa = I < nbr ? __builtin_amdgcn_readfirstlane(q.sa) : -1;
+    q.sb = J < nbr ? __builtin_amdgcn_readfirstlane(q.sb) : -1;
+    q.sd = Rd < nbr ? __builtin_amdgcn_readfirstlane(q.sd) : -1;
+  };
+
+  // quarter kq (k = 16 kq .. 16 kq + 15) of operand w of q into stage st:
+  // eight load instructions of 1 KB (8 kcol rows or 2 krow rows each)
+  const double *pool = static_cast<const double *>(a.xpool);
+  auto dma = [&](const StK &q, int kq, double (*st)[QS]) {
+    const int32_t so = q.sd >= 0 ? q.sd : 0;  // absent: slot 0, never multiplied
+    const char *blkp = reinterpret_cast<const char *>(pool + (int64_t)so * BB);
+    char *dst = reinterpret_cast<char *>(&st[wave][0]);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      int gchunk;
+      if (q.kd) {
+        const int r = 8 * i + (lane >> 3), p = lane & 7;
+        gchunk = r * 32 + 8 * kq + qcol_pos(r, p);
+      } else {
+        const int kr = 2 * i + (lane >> 5), p = lane & 31;
+        gchunk = (16 * kq + kr) * 32 + qrow_pos(kr, p);
+      }
+      __builtin_amdgcn_global_load_lds(blkp + gchunk * 16, dst + i * 1024, 16, 0, 0);
+    }
+  };
+
+  auto compute = [&](const StK &q, double (*st)[QS]) {
+    if (pos < 0 || q.sa < 0 || q.sb < 0) return;
+    mma_quarter(acc, reinterpret_cast<const char *>(st), ia * QS * 8, (2 + jb) * QS * 8, q.ka, q.kb, lane);
+  };
+
+  // quarters of K alternate between the stages; each iteration of the loop
+  // takes quarters 2 h, 2 h + 1 of K and loads the following two
+  int nk = 0;
+  StK q, qn;
+  if (next_k(q)) {
+    fin_k(q);
+    dma(q, 0, S0);
+    int h = 0;
+    bool more = true;
+    while (true) {
+      __syncthreads();  // quarter 2 h in S0 (every wave waited for its loads); S1 free
+      if (h == 1) more = next_k(qn);
+      dma(q, 2 * h + 1, S1);
+      compute(q, S0);
+      if (h == 1 && more) fin_k(qn);
+      __syncthreads();  // quarter 2 h + 1 in S1; S0 free
+      if (h == 0)
+        dma(q, 2, S0);
+      else if (more)
+        dma(qn, 0, S0);
+      compute(q, S1);
+      if (h == 1) {
+        if (pos >= 0 && q.sa >= 0 && q.sb >= 0) ++nk;
+        if (!more) break;
+        q = qn;
+      }
+      h ^= 1;
+    }
+  }
+  // the block's sums over rows 0..31 and 32..63 separately, added in that
+  // order (the same rounding as two waves of 32 rows each)
+  if (pos >= 0) {
+    const auto rowf = [](int g, int v) { return MF<double>::row(g, v); };
+    d4 lo[2][4], hi[2][4];
+#pragma unroll
+    for (int m = 0; m < 2; ++m)
+#pragma unroll
+      for (int n = 0; n < 4; ++n) {
+        lo[m][n] = acc[m][n];
+        hi[m][n] = acc[2 + m][n];
+      }
+    const EpiSums p0 = epilogue_rows<double, double, 2>(lo, a, I, J, pos, 0, rowf);
+    const EpiSums p1 = epilogue_rows<double, double, 2>(hi, a, I, J, pos, 32, rowf);
+    if (lane == 0) {
+      double *p = a.parts + (int64_t)pos * NPART;
+      p[0] = p0.e2 + p1.e2;
+      p[1] = p0.tx + p1.tx;
+      p[2] = p0.ts + p1.ts;
+      p[3] = p0.nr + p1.nr;
+      p[4] = (double)nk;
+    }
+  }
+}
+
+}  // namespace
+
+void launch_square_f64_lds(Ctx &c, const TileArgs &a) {
+  if (a.ntiles <= 0) return;
+  if (a.xprec != P64 || a.oprec != P64 || a.ypool != a.xpool || a.npass != 1 || a.xanti || a.yanti || a.tb != 2)
+    fail(SP2_ERR_INVALID_ARG, "FP64 LDS-load square: plain FP64 squares on 2 x 2 tiles only");
+  k_square_f64_lds<<<(unsigned)(8 * a.xcd_chunk), 256, 0, c.stream>>>(a);
+  SP2_LAUNCH_CHECK();
+}
+
+}  // namespace sp2

@@ -227,3 +227,24 @@ def test_bf16x3_tile_edges_bitwise_pair(gpu_lib, monkeypatch, sign, anti):
     assert np.array_equal(out["2"][1], out["4"][1])
     assert np.array_equal(out["2"][0], out["4"][0])
     assert out["2"][2] == out["4"][2]
+
+
+@pytest.mark.parametrize("n,dens,seed", [(200, 1.0, 1), (1050, 1.0, 4), (1150, 0.3, 5), (2000, 0.08, 6)])
+def test_f64_lds_kernel_bitwise(gpu_lib, monkeypatch, n, dens, seed):
+    """The FP64 square with operands loaded straight to LDS and the
+    register-staged one accumulate in the same order: bit-identical squares and
+    sums, on ragged block counts (4, 17, 18, 32 block rows; 17 leaves tiles
+    with an absent second row / column) and on sparse patterns."""
+    sp2 = gpu_lib
+    X = sp2.BsrMatrix.from_host(random_sym_bsr(n, dens, seed=seed, std=0.1))
+    out = {}
+    for k in ("tile", "lds"):
+        if k == "tile":
+            monkeypatch.setenv("SP2_F64_KERNEL", "tile")
+        else:
+            monkeypatch.delenv("SP2_F64_KERNEL", raising=False)
+        Y, sums = sp2.square_step(X, 0.1, 0.2, -0.3, "fp64")
+        out[k] = (Y.val.cpu().numpy(), Y.col_idx.cpu().numpy(), sums)
+    assert np.array_equal(out["tile"][1], out["lds"][1])
+    assert np.array_equal(out["tile"][0].view(np.uint64), out["lds"][0].view(np.uint64))
+    assert out["tile"][2] == out["lds"][2]
