@@ -67,7 +67,9 @@ extern "C" {
 #define SP2_BLOCK 64
 
 /* precision of the bulk squares */
-#define SP2_PREC_FP64 0   /* every square in FP64 MFMA */
+#define SP2_PREC_FP64 0   /* every square in FP64 MFMA (the plain FP64 square loads its operands straight
+                             to LDS; SP2_F64_KERNEL=tile in the environment selects the register-staged
+                             kernel, bit-identical) */
 #define SP2_PREC_FP32 1   /* FP32 MFMA squares (FP32 storage) until e_i < switch_tol, then FP64 */
 #define SP2_PREC_BF16X3 2 /* BF16 hi/lo split MFMA (hi*hi + hi*lo + lo*hi, FP32 accumulate), then FP64.
                              Products whose output pattern holds >= 35% of the upper blocks run on
