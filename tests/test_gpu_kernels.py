@@ -229,11 +229,13 @@ def test_bf16x3_tile_edges_bitwise_pair(gpu_lib, monkeypatch, sign, anti):
     assert out["2"][2] == out["4"][2]
 
 
-@pytest.mark.parametrize("n,dens,seed", [(200, 1.0, 1), (1050, 1.0, 4), (1150, 0.3, 5), (2000, 0.08, 6)])
+@pytest.mark.parametrize("n,dens,seed", [(30, 1.0, 7), (64, 1.0, 8), (100, 1.0, 9), (130, 1.0, 10),
+                                         (200, 1.0, 1), (1050, 1.0, 4), (1150, 0.3, 5), (2000, 0.08, 6)])
 def test_f64_lds_kernel_bitwise(gpu_lib, monkeypatch, n, dens, seed):
     """The FP64 square with operands loaded straight to LDS and the
     register-staged one accumulate in the same order: bit-identical squares and
-    sums, on ragged block counts (4, 17, 18, 32 block rows; 17 leaves tiles
+    sums, from one partial block up (1, 1, 2, 3 block rows), on ragged block
+    counts (4, 17, 18, 32 block rows; 17 leaves tiles
     with an absent second row / column) and on sparse patterns."""
     sp2 = gpu_lib
     X = sp2.BsrMatrix.from_host(random_sym_bsr(n, dens, seed=seed, std=0.1))
