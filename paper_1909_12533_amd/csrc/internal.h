@@ -218,7 +218,7 @@ struct TileArgs {
 };
 int64_t build_tiles(Ctx &c, const int32_t *oidx, int nbr, Buf &tiles, int tb = 2);
 void launch_square_tile(Ctx &c, int mode, const TileArgs &a);
-// the plain FP64 square with operands loaded straight to LDS (kernels_f64.hip)
+// FP64 squares and products with operands loaded straight to LDS (kernels_f64.hip)
 void launch_square_f64_lds(Ctx &c, const TileArgs &a);
 void launch_square_tile_bf16x3(Ctx &c, const TileArgs &a);  // kernels_bf16x3.hip
 // split the stored blocks of an FP32 pool into bf16 hi/lo images of the block

@@ -59,7 +59,7 @@ __device__ __forceinline__ int frag_off(bool kcol, int r, int k) {
 }
 
 __device__ __forceinline__ void mma_quarter(d4 (&acc)[4][4], const char *st, int oa, int ob, bool ka, bool kb,
-                                            int lane) {
+                                            bool na, bool nb, int lane) {
   const int l16 = lane & 15;
   const int da = ka ? 8 : 512, db = kb ? 8 : 512;
 #pragma unroll
@@ -71,12 +71,20 @@ __device__ __forceinline__ void mma_quarter(d4 (&acc)[4][4], const char *st, int
       const int o = oa + frag_off(ka, 16 * m + l16, k);
       fa[m][0] = *reinterpret_cast<const double *>(st + o);
       fa[m][1] = *reinterpret_cast<const double *>(st + o + da);
+      if (na) {
+        fa[m][0] = -fa[m][0];
+        fa[m][1] = -fa[m][1];
+      }
     }
 #pragma unroll
     for (int n = 0; n < 4; ++n) {
       const int o = ob + frag_off(kb, 16 * n + l16, k);
       fb[n][0] = *reinterpret_cast<const double *>(st + o);
       fb[n][1] = *reinterpret_cast<const double *>(st + o + db);
+      if (nb) {
+        fb[n][0] = -fb[n][0];
+        fb[n][1] = -fb[n][1];
+      }
     }
 #pragma unroll
     for (int s = 0; s < 2; ++s)
@@ -87,6 +95,9 @@ __device__ __forceinline__ void mma_quarter(d4 (&acc)[4][4], const char *st, int
   }
 }
 
+// GEN: general product (second operand Y, a second pass with the roles
+// swapped and its sign, antisymmetric operands); otherwise the square X X.
+template <typename TO, bool GEN>
 __global__ __launch_bounds__(256, 2) void k_square_f64_lds(TileArgs a) {
   __shared__ __align__(16) double S0[4][QS];  // even quarters: A0, A1, B0, B1
   __shared__ __align__(16) double S1[4][QS];  // odd quarters
@@ -109,19 +120,25 @@ __global__ __launch_bounds__(256, 2) void k_square_f64_lds(TileArgs a) {
 #pragma unroll
     for (int n = 0; n < 4; ++n) acc[m][n] = d4{0, 0, 0, 0};
 
-  // K over the union of the four blocks' K sets; once exhausted it keeps
-  // returning false
+  // K over the union of the four blocks' K sets (rows I0, I0 + 1 of the left
+  // operand, columns J0, J0 + 1 of the right one); with two passes the scan
+  // restarts with the operands swapped; once exhausted it keeps returning false
+  const uint32_t *ybits = GEN ? a.ybits : a.bits;
   const uint32_t *bI0 = a.bits + (int64_t)I0 * W, *bI1 = a.bits + (int64_t)(has_i1 ? I0 + 1 : I0) * W;
-  const uint32_t *bJ0 = a.bits + (int64_t)J0 * W, *bJ1 = a.bits + (int64_t)(has_j1 ? J0 + 1 : J0) * W;
-  int wi = -1;
+  const uint32_t *bJ0 = ybits + (int64_t)J0 * W, *bJ1 = ybits + (int64_t)(has_j1 ? J0 + 1 : J0) * W;
+  int wi = -1, pass = 0;
   uint32_t mask = 0u;
   // staged K as one wave sees it: the slots of its own A and B blocks, the
-  // slot of the operand it loads (operand w: A0, A1, B0, B1) and the
-  // orientations (kcol) of those three
+  // slot of the operand it loads (operand w: A0, A1, B0, B1), the
+  // orientations (kcol) of those three, the pass (left operand X, or Y) and
+  // the sign flips of the wave's A and B blocks (antisymmetric lower block,
+  // subtracted second pass)
   struct StK {
     int K;
     int32_t sa, sb, sd;
     bool ka, kb, kd;
+    int kp;
+    bool na, nb;
   };
   const int Rd = wave < 2 ? I0 + wave : J0 + wave - 2;  // block row of the operand this wave loads
   // a zero the compiler takes for a per-lane value: the slot loads below then
@@ -132,8 +149,17 @@ __global__ __launch_bounds__(256, 2) void k_square_f64_lds(TileArgs a) {
     while (mask == 0u) {
       ++wi;
       if (wi >= W) {
-        wi = W;
-        return false;
+        if (!GEN || pass + 1 >= a.npass) {
+          wi = W;
+          return false;
+        }
+        ++pass;
+        wi = -1;
+        bI0 = a.ybits + (int64_t)I0 * W;
+        bI1 = a.ybits + (int64_t)(has_i1 ? I0 + 1 : I0) * W;
+        bJ0 = a.bits + (int64_t)J0 * W;
+        bJ1 = a.bits + (int64_t)(has_j1 ? J0 + 1 : J0) * W;
+        continue;
       }
       const uint32_t ra = bI0[wi] | (has_i1 ? bI1[wi] : 0u);
       const uint32_t rb = bJ0[wi] | (has_j1 ? bJ1[wi] : 0u);
@@ -145,13 +171,23 @@ __global__ __launch_bounds__(256, 2) void k_square_f64_lds(TileArgs a) {
     // the slot loads are only issued here; fin_k makes them wave-uniform
     // after the MFMAs of a quarter, so their latency is hidden (rows past the
     // last block row read row 0 and are replaced by -1 in fin_k)
-    const int32_t *im = a.idxmap + vz;
-    q.sa = im[(int64_t)(I < nbr ? I : 0) * nbr + K];
-    q.sb = im[(int64_t)(J < nbr ? J : 0) * nbr + K];
+    const int kp = GEN ? pass : 0;
+    const int32_t *li = (kp ? a.yidxmap : a.idxmap) + vz;
+    const int32_t *ri = (GEN ? (kp ? a.idxmap : a.yidxmap) : a.idxmap) + vz;
+    q.sa = li[(int64_t)(I < nbr ? I : 0) * nbr + K];
+    q.sb = ri[(int64_t)(J < nbr ? J : 0) * nbr + K];
     q.ka = !(I > K);
     q.kb = K > J;
-    q.sd = im[(int64_t)(Rd < nbr ? Rd : 0) * nbr + K];
+    q.sd = (wave < 2 ? li : ri)[(int64_t)(Rd < nbr ? Rd : 0) * nbr + K];
     q.kd = wave < 2 ? !(Rd > K) : (K > Rd);
+    q.kp = kp;
+    if (GEN) {
+      const bool la = kp ? a.yanti : a.xanti, ra = kp ? a.xanti : a.yanti;
+      q.na = (la && I > K) != (kp && a.neg2);
+      q.nb = ra && K > J;
+    } else {
+      q.na = q.nb = false;
+    }
     return true;
   };
   auto fin_k = [&](StK &q) {
@@ -162,9 +198,11 @@ __global__ __launch_bounds__(256, 2) void k_square_f64_lds(TileArgs a) {
 
   // quarter kq (k = 16 kq .. 16 kq + 15) of operand w of q into stage st:
   // eight load instructions of 1 KB (8 kcol rows or 2 krow rows each)
-  const double *pool = static_cast<const double *>(a.xpool);
+  const double *xp = static_cast<const double *>(a.xpool);
+  const double *yp = static_cast<const double *>(GEN ? a.ypool : a.xpool);
   auto dma = [&](const StK &q, int kq, double (*st)[QS]) {
     const int32_t so = q.sd >= 0 ? q.sd : 0;  // absent: slot 0, never multiplied
+    const double *pool = ((wave < 2) == !(GEN && q.kp)) ? xp : yp;
     const char *blkp = reinterpret_cast<const char *>(pool + (int64_t)so * BB);
     char *dst = reinterpret_cast<char *>(&st[wave][0]);
 #pragma unroll
@@ -183,7 +221,8 @@ __global__ __launch_bounds__(256, 2) void k_square_f64_lds(TileArgs a) {
 
   auto compute = [&](const StK &q, double (*st)[QS]) {
     if (pos < 0 || q.sa < 0 || q.sb < 0) return;
-    mma_quarter(acc, reinterpret_cast<const char *>(st), ia * QS * 8, (2 + jb) * QS * 8, q.ka, q.kb, lane);
+    mma_quarter(acc, reinterpret_cast<const char *>(st), ia * QS * 8, (2 + jb) * QS * 8, q.ka, q.kb, GEN && q.na,
+                GEN && q.nb, lane);
   };
 
   // quarters of K alternate between the stages; each iteration of the loop
@@ -227,8 +266,8 @@ __global__ __launch_bounds__(256, 2) void k_square_f64_lds(TileArgs a) {
         lo[m][n] = acc[m][n];
         hi[m][n] = acc[2 + m][n];
       }
-    const EpiSums p0 = epilogue_rows<double, double, 2>(lo, a, I, J, pos, 0, rowf);
-    const EpiSums p1 = epilogue_rows<double, double, 2>(hi, a, I, J, pos, 32, rowf);
+    const EpiSums p0 = epilogue_rows<double, TO, 2>(lo, a, I, J, pos, 0, rowf);
+    const EpiSums p1 = epilogue_rows<double, TO, 2>(hi, a, I, J, pos, 32, rowf);
     if (lane == 0) {
       double *p = a.parts + (int64_t)pos * NPART;
       p[0] = p0.e2 + p1.e2;
@@ -244,9 +283,19 @@ __global__ __launch_bounds__(256, 2) void k_square_f64_lds(TileArgs a) {
 
 void launch_square_f64_lds(Ctx &c, const TileArgs &a) {
   if (a.ntiles <= 0) return;
-  if (a.xprec != P64 || a.oprec != P64 || a.ypool != a.xpool || a.npass != 1 || a.xanti || a.yanti || a.tb != 2)
-    fail(SP2_ERR_INVALID_ARG, "FP64 LDS-load square: plain FP64 squares on 2 x 2 tiles only");
-  k_square_f64_lds<<<(unsigned)(8 * a.xcd_chunk), 256, 0, c.stream>>>(a);
+  if (a.xprec != P64 || a.tb != 2) fail(SP2_ERR_INVALID_ARG, "FP64 LDS-load square: FP64 operands, 2 x 2 tiles");
+  const bool gen = a.ypool != a.xpool || a.npass != 1 || a.xanti || a.yanti;
+  if (gen && !(a.ypool && a.yidxmap && a.ybits && (a.npass == 1 || a.npass == 2)))
+    fail(SP2_ERR_INVALID_ARG, "tiled product: incomplete second operand");
+  const unsigned g = (unsigned)(8 * a.xcd_chunk);
+  if (a.oprec == P32) {  // FP64 arithmetic, result rounded to FP32 (the correction's commutator)
+    if (!gen) fail(SP2_ERR_INVALID_ARG, "FP64 square with FP32 output is for products only");
+    k_square_f64_lds<float, true><<<g, 256, 0, c.stream>>>(a);
+  } else if (gen) {
+    k_square_f64_lds<double, true><<<g, 256, 0, c.stream>>>(a);
+  } else {
+    k_square_f64_lds<double, false><<<g, 256, 0, c.stream>>>(a);
+  }
   SP2_LAUNCH_CHECK();
 }
 

@@ -268,9 +268,9 @@ int tile_edge(int mode, int64_t nout, int nbr) {
   return (double)nout >= 0.35 * 0.5 * (double)nbr * (double)(nbr + 1) ? 4 : 2;
 }
 
-// The plain FP64 square runs k_square_f64_lds (operands loaded straight to
-// LDS, bit-identical to k_square_tile); SP2_F64_KERNEL=tile in the
-// environment selects k_square_tile instead.
+// FP64 squares and pair products run k_square_f64_lds (operands loaded
+// straight to LDS, bit-identical to k_square_tile); SP2_F64_KERNEL=tile in
+// the environment selects k_square_tile instead.
 bool use_f64_lds() {
   const char *e = std::getenv("SP2_F64_KERNEL");
   return !(e && e[0] == 't');
@@ -416,7 +416,10 @@ SquareOut pair_product(Ctx &c, const DMat &X, const Maps &mx, const DMat &Y, con
   ta.parts = r.parts.as<double>();
   EventPair ev;
   SP2_HIP(hipEventRecord(ev.a, c.stream));
-  launch_square_tile(c, po.mode, ta);
+  if (po.mode == M_F64 && tb == 2 && use_f64_lds())
+    launch_square_f64_lds(c, ta);
+  else
+    launch_square_tile(c, po.mode, ta);
   SP2_HIP(hipEventRecord(ev.b, c.stream));
   Buf sums = c.alloc(sizeof(double) * NPART);
   launch_reduce_parts(c, ta.parts, nout, NPART, sums.as<double>());

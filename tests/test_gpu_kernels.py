@@ -250,3 +250,36 @@ def test_f64_lds_kernel_bitwise(gpu_lib, monkeypatch, n, dens, seed):
     assert np.array_equal(out["tile"][1], out["lds"][1])
     assert np.array_equal(out["tile"][0].view(np.uint64), out["lds"][0].view(np.uint64))
     assert out["tile"][2] == out["lds"][2]
+
+
+@pytest.mark.parametrize("sign,anti,with_g", [(1, False, False), (-1, False, False), (-1, True, False),
+                                              (1, False, True), (-1, True, True)])
+def test_f64_lds_kernel_bitwise_pair(gpu_lib, monkeypatch, sign, anti, with_g):
+    """Two-operand mode of the FP64 LDS-loaded kernel (anticommutator,
+    commutator, antisymmetric right operand, a I + b G term): bit-identical to
+    the register-staged kernel, on a ragged block count (18 block rows) with
+    two sparse patterns."""
+    sp2 = gpu_lib
+    n = 1100
+    Xh = random_sym_bsr(n, 0.7, seed=8, std=0.1)
+    Yh = random_sym_bsr(n, 0.6, seed=9, std=0.1)
+    if anti:
+        I = Yh.rows()
+        v = Yh.val.copy()
+        d = I == Yh.col_idx
+        v[d] = v[d] - v[d].transpose(0, 2, 1)
+        Yh = Yh.with_values(v)
+    X, Y = sp2.BsrMatrix.from_host(Xh), sp2.BsrMatrix.from_host(Yh)
+    G = X if with_g else None
+    coef = dict(a=0.3, b=-0.7, c=1.1) if with_g else {}
+    out = {}
+    for k in ("tile", "lds"):
+        if k == "tile":
+            monkeypatch.setenv("SP2_F64_KERNEL", "tile")
+        else:
+            monkeypatch.delenv("SP2_F64_KERNEL", raising=False)
+        P, sums = sp2.pair_product(X, Y, G=G, sign=sign, y_antisym=anti, precision="fp64", **coef)
+        out[k] = (P.val.cpu().numpy(), P.col_idx.cpu().numpy(), sums)
+    assert np.array_equal(out["tile"][1], out["lds"][1])
+    assert np.array_equal(out["tile"][0].view(np.uint64), out["lds"][0].view(np.uint64))
+    assert out["tile"][2] == out["lds"][2]
