@@ -1,14 +1,17 @@
-// FP64 square with operands loaded straight to LDS (the symmetric square of
-// Algorithm 2 in FP64, the method's reference arithmetic).
+// FP64 square and two-operand products with operands loaded straight to LDS
+// (the symmetric square of Algorithm 2 in FP64, the method's reference
+// arithmetic; the products X Y +- Y X of the adjoint and the correction).
 //
 // One workgroup of four waves per 2 x 2 tile of output blocks; wave w owns the
 // whole 64 x 64 block (I0 + w / 2, J0 + w % 2) in 4 x 4 MFMA accumulator tiles.
 // K runs ascending over the union of the tile's K sets and each K is taken in
 // four 16-deep k quarters, so every output element accumulates in the same
-// order as in k_square_tile<double, double, false, 8> (K ascending, 16-deep k
-// chunks in order, k = 4 g + s within an MFMA): the two give bit-identical
-// results, the block sums included (added over rows 0..31 and 32..63 in that
-// order).
+// order as in k_square_tile<double, TO, GEN, 8> (K ascending, the second
+// pass after the first, 16-deep k chunks in order, k = 4 g + s within an
+// MFMA): the two give bit-identical results, the block sums included (added
+// over rows 0..31 and 32..63 in that order).  Sign flips of antisymmetric
+// lower blocks and of a subtracted second pass are exact negations of the
+// fragments after their LDS read.
 //
 // Staging: each quarter of the four operand blocks (A0, A1, B0, B1; 8 KB
 // each) is loaded by global_load_lds_dwordx4 straight into LDS, wave w
