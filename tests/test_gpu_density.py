@@ -49,6 +49,27 @@ def test_dense_c0(gpu_lib, accel):
     assert r.stop_reason == ref.stop_reason
 
 
+@pytest.mark.parametrize("accel,hb,lb", [(False, -0.05, 0.05), (False, -0.02, 0.02), (True, -0.02, 0.02)])
+def test_stop_by_criterion_before_n_max(gpu_lib, accel, hb, lb):
+    """Algorithm 2's stopping test on the GPU: with loose homo/lumo bounds the
+    untruncated dense run converges before n_max and the criterion, not n_max,
+    ends it at the oracle's index (pinned on the CPU by the scalar eigenvalue
+    iteration)."""
+    sp2 = gpu_lib
+    Fd, lam, Y = dense_spectrum(512, seed=0)
+    ref = O.sp2(Fd, 256, -1.0, 1.0, hb, lb, accel=accel, trunc_norm=O.TRUNC_NONE)
+    assert ref.stop_reason == "criterion"
+    F = sp2.BsrMatrix.from_host(dense_to_bsr(Fd))
+    r = sp2.density(F, 256, -1.0, 1.0, hb, lb, accel=accel, trunc_norm="none")
+    print(f"accel={accel} bounds={hb},{lb}: gpu n={r.n_iter} ({r.stop_reason}) oracle n={ref.n} n_max={r.n_max}")
+    assert r.stop_reason == "criterion"
+    assert r.n_iter == ref.n
+    if not accel:
+        assert r.n_iter < r.n_max
+    assert r.status == 0
+    _compare_runs(r, ref)
+
+
 @pytest.mark.parametrize("L,norm,tau,cbs", [
     (6, "frobinf", 1e-3, 256),
     (6, "frob", 3e-3, 4096),
