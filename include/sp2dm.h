@@ -247,6 +247,46 @@ int sp2_density(sp2_ctx *ctx, const sp2_bsr *F, int64_t n_occ, double lmin, doub
                 sp2_bsr **D_out, double *homo_est, double *lumo_est, sp2_stats *stats,
                 sp2_tape **tape);
 
+/* The expansion one unit of work at a time.  sp2_density_begin,
+ * sp2_density_step and sp2_density_end perform exactly the work of
+ * sp2_density (same arithmetic, same results), split so that a caller can run
+ * it in pieces (interleave other work, watch progress, time single
+ * iterations):
+ *   begin  Step 1 (schedule) and Algorithm 1 (X_0 = (lmax I - F) / w and its
+ *          truncation); arguments as sp2_density; *solver receives the handle;
+ *   step   one iteration of Algorithm 2 (square of X~_i with the fused
+ *          update, e_i and t_i, the stopping test, truncation of X_{i+1}) or,
+ *          once the expansion has stopped, one block product of the subspace
+ *          correction (opt->correct > 0); *info (may be NULL) describes the
+ *          step, info->done = 1 when nothing is left; calling it after that
+ *          is an error;
+ *   end    Step 3 and the outputs (D_out, estimates, stats, tape) exactly as
+ *          sp2_density; only valid after *done = 1.
+ * F is borrowed until sp2_density_end returns.  The handle is released with
+ * sp2_solver_free (also after end, and after any error: a failed step leaves
+ * it unusable).  stats->time_s is the time spent inside the three calls. */
+typedef struct sp2_solver sp2_solver;
+#define SP2_STEP_ITERATION 1  /* one iteration of Algorithm 2 */
+#define SP2_STEP_CORRECTION 2 /* one product of the subspace correction */
+typedef struct {
+  int32_t done;           /* 1: nothing left, call sp2_density_end */
+  int32_t kind;           /* SP2_STEP_* */
+  int32_t iteration;      /* i of the square of X~_i (SP2_STEP_ITERATION), else -1 */
+  int32_t precision;      /* SP2_PREC_* of the step's dominant block products */
+  double flops;           /* algorithmic flops of the step's block products (2 * 64^3 each) */
+  double wall_s;          /* time spent in the call */
+  double kernel_s[3];     /* device time of the MFMA product kernels by arithmetic (index SP2_PREC_*),
+                             from HIP events on the context stream */
+  double kernel_flops[3]; /* algorithmic flops of those launches, same index (a recomputed iterate's
+                             square counts here but not in flops) */
+} sp2_step_info;
+int sp2_density_begin(sp2_ctx *ctx, const sp2_bsr *F, int64_t n_occ, double lmin, double lmax,
+                      const double *homo_ub, const double *lumo_lb, const sp2_options *opt, sp2_solver **solver);
+int sp2_density_step(sp2_ctx *ctx, sp2_solver *solver, sp2_step_info *info);
+int sp2_density_end(sp2_ctx *ctx, sp2_solver *solver, sp2_bsr **D_out, double *homo_est, double *lumo_est,
+                    sp2_stats *stats, sp2_tape **tape);
+void sp2_solver_free(sp2_ctx *ctx, sp2_solver *solver);
+
 /* Vector-Jacobian product of the recorded (frozen schedule and masks) map
  * F -> D: Fbar = (dL/dF) for L = tr(W D), W symmetric in upper BSR on any
  * pattern.  X~_i are recomputed from the tape's checkpoints; recomputed

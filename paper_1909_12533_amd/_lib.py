@@ -25,7 +25,8 @@ EXPORTS = [
     "sp2_version", "sp2_options_default", "sp2_create", "sp2_destroy", "sp2_set_allocator", "sp2_trim",
     "sp2_last_error", "sp2_gershgorin", "sp2_density", "sp2_vjp", "sp2_jvp", "sp2_replay", "sp2_tape_info",
     "sp2_square_step", "sp2_truncate", "sp2_bsr_copy", "sp2_bsr_free", "sp2_tape_free", "sp2_schedule",
-    "sp2_homo_lumo", "sp2_pair_product", "sp2_matrix_norms",
+    "sp2_homo_lumo", "sp2_pair_product", "sp2_matrix_norms", "sp2_density_begin", "sp2_density_step",
+    "sp2_density_end", "sp2_solver_free",
 ]
 
 
@@ -108,6 +109,22 @@ class sp2_stats(C.Structure):
     ]
 
 
+STEP_ITERATION, STEP_CORRECTION = 1, 2
+
+
+class sp2_step_info(C.Structure):
+    _fields_ = [
+        ("done", C.c_int32),
+        ("kind", C.c_int32),
+        ("iteration", C.c_int32),
+        ("precision", C.c_int32),
+        ("flops", C.c_double),
+        ("wall_s", C.c_double),
+        ("kernel_s", C.c_double * 3),
+        ("kernel_flops", C.c_double * 3),
+    ]
+
+
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
 FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
 
@@ -144,6 +161,16 @@ def load(path: str = LIB_PATH):
     lib.sp2_density.argtypes = [C.c_void_p, P(sp2_bsr), C.c_int64, C.c_double, C.c_double, P(C.c_double),
                                 P(C.c_double), P(sp2_options), P(P(sp2_bsr)), P(C.c_double), P(C.c_double),
                                 P(sp2_stats), P(C.c_void_p)]
+    lib.sp2_density_begin.restype = C.c_int
+    lib.sp2_density_begin.argtypes = [C.c_void_p, P(sp2_bsr), C.c_int64, C.c_double, C.c_double, P(C.c_double),
+                                      P(C.c_double), P(sp2_options), P(C.c_void_p)]
+    lib.sp2_density_step.restype = C.c_int
+    lib.sp2_density_step.argtypes = [C.c_void_p, C.c_void_p, P(sp2_step_info)]
+    lib.sp2_density_end.restype = C.c_int
+    lib.sp2_density_end.argtypes = [C.c_void_p, C.c_void_p, P(P(sp2_bsr)), P(C.c_double), P(C.c_double),
+                                    P(sp2_stats), P(C.c_void_p)]
+    lib.sp2_solver_free.restype = None
+    lib.sp2_solver_free.argtypes = [C.c_void_p, C.c_void_p]
     for name in ("sp2_vjp", "sp2_jvp", "sp2_replay"):
         f = getattr(lib, name)
         f.restype = C.c_int

@@ -80,6 +80,10 @@ struct Ctx {
   std::multimap<size_t, void *> cache;  // released buffers, reused by size
   size_t cached_bytes = 0;
   size_t live_bytes = 0, peak_bytes = 0;
+  // device time (HIP events) and algorithmic flops of the MFMA product kernels
+  // launched so far, by arithmetic (Mode); read by the stepped solver
+  double kern_s[3] = {0.0, 0.0, 0.0};
+  double kern_flops[3] = {0.0, 0.0, 0.0};
   double *h_pinned = nullptr;  // pinned host staging for small device->host reads
   size_t h_pinned_bytes = 0;
 

@@ -346,6 +346,8 @@ SquareOut square_step(Ctx &c, const DMat &X, const Maps &m, int mode, int oprec,
   float ms = 0.0f;
   SP2_HIP(hipEventElapsedTime(&ms, ev.a, ev.b));
   r.kernel_s = 1e-3 * (double)ms;
+  c.kern_s[mode] += r.kernel_s;
+  c.kern_flops[mode] += r.sums[4] * 2.0 * B * B * B;
   return r;
 }
 
@@ -427,6 +429,8 @@ SquareOut pair_product(Ctx &c, const DMat &X, const Maps &mx, const DMat &Y, con
   float ms = 0.0f;
   SP2_HIP(hipEventElapsedTime(&ms, ev.a, ev.b));
   r.kernel_s = 1e-3 * (double)ms;
+  c.kern_s[po.mode] += r.kernel_s;
+  c.kern_flops[po.mode] += r.sums[4] * 2.0 * B * B * B;
   return r;
 }
 
@@ -650,133 +654,8 @@ struct CorrStats {
   int64_t max_nnzb = 0;
 };
 
-// Occupied-subspace correction rounds (the operation documented with
-// sp2_options.correct): Delta = [D, [D, F]], dD = J Delta along the stored
-// X~_0 .. X~_{n-1} (derivative of the polynomial steps, blocks dropped within
-// corr_tol), D <- FP64 purification of D + dD.  The commutator C = [D, F] is
-// formed in FP64 (it is small: the difference of two O(1) products); [D, C]
-// and the derivative steps use the arithmetic the expansion used for each X~_i.
 DMat replay_step(Ctx &c, const Tape &t, int i, const DMat &Xprev);
 DMat checkpoint_copy(const Tape &t, int i);
-
-// ct records X~_0 .. X~_{nseq-1} (masks, polynomials, arithmetic) with
-// copies of a prefix of them; the others are recomputed in order.
-DMat subspace_correction(Ctx &c, const DMat &F, DMat D, const Tape &ct, int nseq, const std::vector<int> &p,
-                         const std::vector<double> &alph, const std::vector<double> &e, double w,
-                         const sp2_options &o, int lowmode, double tau_n, CorrStats &cs) {
-  const double beta = o.corr_tol > 0.0 ? o.corr_tol : 1e-9;
-  const double fl = 2.0 * B * B * B;
-  // Once an iterate is close to a projector P (e_i small), the remaining
-  // derivative steps map dX to P dX (I - P) + (I - P) dX P plus parts inside
-  // the two subspaces, which the purification removes: they change the
-  // correction only at relative order e_i and are skipped.
-  int n = nseq;
-  for (int i = 1; i < n; ++i)
-    if (e[i] < 1e-3) {
-      n = i;
-      break;
-    }
-  auto note = [&](const DMat &M) { cs.max_nnzb = std::max(cs.max_nnzb, M.pat.nnzb); };
-  auto drop = [&](DMat &M, const SquareOut &so) {
-    note(M);
-    Buf nrm2 = column(c, so.parts, M.pat.nnzb, 3);
-    truncate_matrix(c, M, nrm2.as<double>(), beta, SP2_TRUNC_FROB, o.coarse_bs);
-  };
-  const int lp = lowmode == M_F64 ? P64 : P32;
-  for (int r = 0; r < o.correct; ++r) {
-    // the symmetric part of D: a low-precision iterate's diagonal blocks carry
-    // antisymmetric rounding noise, which the correction must not see
-    if (r == 0) {
-      D = compact_values(c, D, D.pool->prec);
-      sym_diag(c, D, 1.0);
-    }
-    // C = D F - F D, antisymmetric, in FP64 arithmetic (stored in the low
-    // precision: the cancellation happens in the accumulators)
-    DMat C;
-    {
-      DMat D64 = as_prec(c, D, P64);
-      Maps mD = build_maps(c, D64.pat, true), mF = build_maps(c, F.pat, true);
-      PairOpt pc;
-      pc.neg2 = true;
-      pc.oprec = lp;
-      SquareOut co = pair_product(c, D64, mD, F, mF, pc);
-      cs.flops += co.sums[4] * fl;
-      C = std::move(co.next);
-      sym_diag(c, C, -1.0);
-      drop(C, co);
-      if (verbose())
-        std::fprintf(stderr, "[sp2] correction: C = [D, F] nnzb=%lld square %.1f ms\n", (long long)C.pat.nnzb,
-                     1e3 * co.kernel_s);
-    }
-    // dX~_0 = -(D C - C D) / w = -Delta / w
-    DMat dX;
-    {
-      DMat Dl = as_prec(c, D, lp), Cl = as_prec(c, C, lp);
-      C = DMat();
-      Maps mD = build_maps(c, Dl.pat, true), mC = build_maps(c, Cl.pat, true);
-      PairOpt pd;
-      pd.neg2 = true;
-      pd.yanti = true;
-      pd.cc = -1.0 / w;
-      pd.mode = lowmode;
-      pd.oprec = lp;
-      SquareOut dd = pair_product(c, Dl, mD, Cl, mC, pd);
-      cs.flops += dd.sums[4] * fl;
-      cs.delta_norm = std::sqrt(std::fmax(dd.sums[0], 0.0));  // no G: sums[0] = ||D C - C D||_F^2
-      dX = std::move(dd.next);
-      drop(dX, dd);
-      if (verbose())
-        std::fprintf(stderr, "[sp2] correction: Delta nnzb=%lld ||Delta||=%.3e product %.1f ms\n",
-                     (long long)dX.pat.nnzb, cs.delta_norm, 1e3 * dd.kernel_s);
-    }
-    // derivative of X_{i+1} = ca I + cb X~_i + cc X~_i^2 along dX~_i
-    DMat Xi;
-    for (int i = 0; i < n; ++i) {
-      Xi = ct.it[i].ckpt ? checkpoint_copy(ct, i) : replay_step(c, ct, i, Xi);
-      const int mi = Xi.pool->prec == P32 ? lowmode : M_F64;
-      DMat G = as_prec(c, dX, Xi.pool->prec);
-      Maps mX = build_maps(c, Xi.pat, true), mG = build_maps(c, G.pat, true);
-      double ca, cb, cc;
-      poly_coeffs(p[i + 1], alph[i + 1], ca, cb, cc);
-      PairOpt pj;
-      pj.G = &G;
-      pj.mg = &mG;
-      pj.cb = cb;
-      pj.cc = cc;
-      pj.mode = mi;
-      pj.oprec = Xi.pool->prec;
-      SquareOut jo = pair_product(c, Xi, mX, G, mG, pj);
-      cs.flops += jo.sums[4] * fl;
-      dX = std::move(jo.next);
-      drop(dX, jo);
-      if (verbose())
-        std::fprintf(stderr, "[sp2] correction: derivative step %d/%d nnzb=%lld%s product %.1f ms\n", i + 1, n,
-                     (long long)dX.pat.nnzb, ct.it[i].ckpt ? "" : " (recomputed iterate)", 1e3 * jo.kernel_s);
-    }
-    cs.step_norm = frob_norm(c, dX);
-    DMat P = add_union(c, D, 1.0, dX, 1.0);
-    note(P);
-    for (int k = 0; k < o.corr_purify; ++k) {
-      double ca, cb, cc;
-      poly_coeffs(k % 2 == 0 ? 1 : 0, 1.0, ca, cb, cc);
-      Maps m = build_maps(c, P.pat, true);
-      SquareOut so = square_step(c, P, m, M_F64, P64, ca, cb, cc);
-      cs.flops += so.sums[4] * fl;
-      cs.e_last = std::sqrt(std::fmax(so.sums[0], 0.0));
-      DMat Pn = std::move(so.next);
-      note(Pn);
-      Buf nrm2 = column(c, so.parts, Pn.pat.nnzb, 3);
-      truncate_matrix(c, Pn, nrm2.as<double>(), tau_n, o.trunc_norm, o.coarse_bs);
-      P = std::move(Pn);
-      if (verbose())
-        std::fprintf(stderr, "[sp2] correction: purification %d e=%.3e square %.1f ms\n", k, cs.e_last,
-                     1e3 * so.kernel_s);
-    }
-    D = std::move(P);
-    cs.rounds++;
-  }
-  return D;
-}
 
 void add_checkpoint(Ctx &c, Tape &t, int i, const DMat &X) {
   auto d = std::make_shared<DMat>(compact_values(c, X, X.pool->prec));
@@ -785,15 +664,87 @@ void add_checkpoint(Ctx &c, Tape &t, int i, const DMat &X) {
   t.n_ckpt++;
 }
 
-int run_density(Ctx &c, const sp2_bsr *Fin, int64_t n_occ, double lmin, double lmax, const double *hub,
-                const double *llb, const sp2_options &o, sp2_bsr **D_out, double *hest, double *lest,
-                sp2_stats *st, sp2_tape **tape_out) {
+constexpr double FL_BLOCK = 2.0 * B * B * B;  // flops of one 64 x 64 x 64 block product
+
+double seconds_since(std::chrono::steady_clock::time_point t0) {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+}
+
+// One density-matrix expansion as a resumable computation.  begin() runs
+// Step 1 and Algorithm 1 (schedule, X_0 and its truncation); each step() runs
+// one iteration of Algorithm 2 (square with the fused update, e_i and t_i,
+// the stopping test, truncation of X_{i+1}) or, after the expansion, one
+// product of the subspace correction; finish() runs Step 3 and returns D.
+struct Solver {
+  Ctx &c;
+  // ---- problem
+  DMat F;  // borrowed
+  int64_t N = 0, n_occ = 0;
+  double lmin = 0.0, lmax = 0.0, w = 1.0;
+  sp2_options o{};
+  int lowmode = M_F64;
+  bool corr = false, low_to_end = false;
+  Sched sch;
+  int n_max = 0;
+  // ---- adjoint tape
+  std::unique_ptr<sp2_tape> tape;
+  int ck_every = 1;
+  int64_t tape_budget = 0;
+  // ---- expansion
+  DMat X;  // X~_i (after the expansion: the current D)
+  int i = 0;
+  std::vector<double> e, t, trv, errF, errM, itime, iflops, ksq, alph{1.0}, taus;
+  std::vector<int> p{-1}, precv;
+  std::vector<int64_t> nnzbv;
+  int switch_iter = -1, n = -1, stop_reason = 0, status = SP2_OK;
+  double alg_flops = 0.0;
+  int64_t max_nnzb = 0, seq_bytes = 0;
+  // ---- iterates recorded for the correction (masks, polynomials, a prefix of copies)
+  Tape ct;
+  int64_t seq_budget = 0;
+  bool seq_full = false;
+  // ---- correction state
+  enum Phase { EXPAND, CORRECT, FINISHED, FAILED };
+  enum CStage { C_COMM, C_DELTA, C_DERIV, C_PURIFY };
+  Phase phase = EXPAND;
+  CStage cstage = C_COMM;
+  int cround = 0, ck = 0, n_deriv = 0;
+  double beta = 1e-9;
+  DMat C, dX, Xi;
+  CorrStats cs;
+  // ---- accounting
+  double busy_s = 0.0;     // time spent inside begin / step / finish
+  double last_flops = 0.0; // algorithmic flops of the last step
+  sp2_step_info info{};    // facts of the last step
+
+  explicit Solver(Ctx &ctx) : c(ctx) {}
+  void begin(const sp2_bsr *Fin, int64_t n_occ_, double lmin_, double lmax_, const double *hub, const double *llb,
+             const sp2_options &opt);
+  bool step();
+  int finish(sp2_bsr **D_out, double *hest, double *lest, sp2_stats *st, sp2_tape **tape_out);
+
+ private:
+  void iterate();
+  void correct_step();
+  void note(const DMat &M) { cs.max_nnzb = std::max(cs.max_nnzb, M.pat.nnzb); }
+  // blocks of a correction intermediate dropped within the Frobenius budget beta
+  void drop(DMat &M, const SquareOut &so) {
+    note(M);
+    Buf nrm2 = column(c, so.parts, M.pat.nnzb, 3);
+    truncate_matrix(c, M, nrm2.as<double>(), beta, SP2_TRUNC_FROB, o.coarse_bs);
+  }
+};
+
+void Solver::begin(const sp2_bsr *Fin, int64_t n_occ_, double lmin_, double lmax_, const double *hub,
+                   const double *llb, const sp2_options &opt) {
+  auto t0 = std::chrono::steady_clock::now();
+  o = opt;
+  n_occ = n_occ_;
+  lmin = lmin_;
+  lmax = lmax_;
   // ---- argument checks ---------------------------------------------------------
-  if (!D_out) fail(SP2_ERR_INVALID_ARG, "D_out is NULL");
-  *D_out = nullptr;
-  if (tape_out) *tape_out = nullptr;
   check_input(Fin, "F");
-  const int64_t N = Fin->n;
+  N = Fin->n;
   if (!(n_occ > 0 && n_occ < N)) fail(SP2_ERR_INVALID_ARG, "n_occ must lie in (0, n)");
   if (!(std::isfinite(lmin) && std::isfinite(lmax) && lmin < lmax))
     fail(SP2_ERR_INVALID_ARG, "need finite lmin < lmax");
@@ -807,34 +758,29 @@ int run_density(Ctx &c, const sp2_bsr *Fin, int64_t n_occ, double lmin, double l
     fail(SP2_ERR_INVALID_ARG, "coarse_bs must be a positive multiple of 64");
   if (!(o.gamma >= 0.0) || !(o.tau_fixed >= 0.0) || std::isnan(o.switch_tol) || !(o.idem_stop >= 0.0))
     fail(SP2_ERR_INVALID_ARG, "tolerances must be >= 0 (switch_tol: any number)");
-  if (st && st->capacity < o.n_max_cap + 1) fail(SP2_ERR_INVALID_ARG, "stats capacity < n_max_cap + 1");
-  if (tape_out && !o.record_tape) fail(SP2_ERR_INVALID_ARG, "a tape needs record_tape = 1");
   if (o.correct < 0 || o.correct > 8) fail(SP2_ERR_INVALID_ARG, "correct must be in [0, 8]");
   if (o.correct > 0 && (o.corr_purify < 1 || o.corr_purify > 16))
     fail(SP2_ERR_INVALID_ARG, "corr_purify must be in [1, 16]");
   if (!(o.corr_tol >= 0.0)) fail(SP2_ERR_INVALID_ARG, "corr_tol must be >= 0");
   if (o.corr_mem < 0) fail(SP2_ERR_INVALID_ARG, "corr_mem must be >= 0");
   if (o.adjoint_precision < -1 || o.adjoint_precision > 2) fail(SP2_ERR_INVALID_ARG, "unknown adjoint_precision");
-  const int lowmode = o.precision == SP2_PREC_FP32 ? M_F32 : (o.precision == SP2_PREC_BF16X3 ? M_BF16X3 : M_F64);
-  const bool corr = o.correct > 0;
+  lowmode = o.precision == SP2_PREC_FP32 ? M_F32 : (o.precision == SP2_PREC_BF16X3 ? M_BF16X3 : M_F64);
+  corr = o.correct > 0;
   // with the correction and no switch tolerance, or with a negative one, the
   // whole expansion stays in the low precision and stops by its own criterion
-  const bool low_to_end = (corr && !(o.switch_tol > 0.0)) || o.switch_tol < 0.0;
+  low_to_end = (corr && !(o.switch_tol > 0.0)) || o.switch_tol < 0.0;
+  beta = o.corr_tol > 0.0 ? o.corr_tol : 1e-9;
 
-  auto t_start = std::chrono::steady_clock::now();
   c.peak_bytes = c.live_bytes;
-  DMat F = borrow_matrix(c, Fin, "F");
+  F = borrow_matrix(c, Fin, "F");
   check_finite(c, Fin->val, Fin->nnzb * (int64_t)BB, "F");
 
   // ---- Step 1 ---------------------------------------------------------------------
-  const double w = lmax - lmin;
-  Sched sch = hub ? make_schedule(lmin, lmax, *hub, *llb, o.accel != 0, o.gamma, o.tau_fixed, o.n_max_cap)
-                  : make_tc2(lmin, lmax, o.tau_fixed, o.n_max_cap);
-  const int n_max = sch.n_max;
+  w = lmax - lmin;
+  sch = hub ? make_schedule(lmin, lmax, *hub, *llb, o.accel != 0, o.gamma, o.tau_fixed, o.n_max_cap)
+            : make_tc2(lmin, lmax, o.tau_fixed, o.n_max_cap);
+  n_max = sch.n_max;
 
-  std::unique_ptr<sp2_tape> tape;
-  int ck_every = 1;
-  int64_t tape_budget = 0;  // device bytes for checkpoints; one that does not fit is skipped
   if (o.record_tape) {
     tape.reset(new sp2_tape());
     tape->ctx = &c;
@@ -853,10 +799,7 @@ int run_density(Ctx &c, const sp2_bsr *Fin, int64_t n_occ, double lmin, double l
   }
 
   // ---- Algorithm 1 ------------------------------------------------------------------
-  DMat X = init_x0(c, F, lmax, w);
-  std::vector<double> e, t, trv, errF, errM, itime, iflops, ksq, alph{1.0}, taus;
-  std::vector<int> p{-1}, precv;
-  std::vector<int64_t> nnzbv;
+  X = init_x0(c, F, lmax, w);
   {
     Buf nrm2 = norms_of(c, X);
     TruncResult tr = truncate_matrix(c, X, nrm2.as<double>(), sch.tau[0], o.trunc_norm, o.coarse_bs);
@@ -865,17 +808,8 @@ int run_density(Ctx &c, const sp2_bsr *Fin, int64_t n_occ, double lmin, double l
     taus.push_back(sch.tau[0]);
   }
   if (lowmode != M_F64) X = compact_values(c, X, P32);
-  int switch_iter = lowmode != M_F64 ? -1 : 0;
+  switch_iter = lowmode != M_F64 ? -1 : 0;
 
-  int n = -1, stop_reason = 0, status = SP2_OK;
-  double alg_flops = 0.0;
-  int64_t max_nnzb = 0, seq_bytes = 0;
-  // X~_0 .. X~_{n-1} for the correction: masks and polynomials of every
-  // iteration, copies of the iterates while they fit in a share of the device
-  // memory (the rest are recomputed during the correction)
-  Tape ct;
-  int64_t seq_budget = 0;
-  bool seq_full = false;
   if (corr) {
     size_t fr = 0, tot = 0;
     SP2_HIP(hipMemGetInfo(&fr, &tot));
@@ -885,160 +819,337 @@ int run_density(Ctx &c, const sp2_bsr *Fin, int64_t n_occ, double lmin, double l
     ct.lmax = lmax;
     ct.w = w;
   }
-  for (int i = 0;; ++i) {
-    auto t_it = std::chrono::steady_clock::now();
-    const int mode = X.pool->prec == P32 ? lowmode : M_F64;
-    if (tape) {
-      tape->it.emplace_back();
-      TapeIter &ti = tape->it.back();
-      ti.mask = clone_pattern(c, X.pat);
-      ti.mask.slot.reset();
-      ti.mode = mode;
-      ti.prec = X.pool->prec;
-      if (i >= 1) {
-        ti.p = p[i];
-        ti.alpha = alph[i];
-        poly_coeffs(p[i], alph[i], ti.ca, ti.cb, ti.cc);
-      }
-      const int64_t ckb = X.pat.nnzb * (int64_t)BB * (X.pool->prec == P64 ? 8 : 4);
-      if (i % ck_every == 0 && (i == 0 || tape->bytes + ckb <= tape_budget)) add_checkpoint(c, *tape, i, X);
-    }
-    nnzbv.push_back(X.pat.nnzb);
-    max_nnzb = std::max(max_nnzb, X.pat.nnzb);
-    precv.push_back(mode == M_F64 ? SP2_PREC_FP64 : o.precision);
+  c.sync();
+  busy_s += seconds_since(t0);
+}
 
-    Maps m = build_maps(c, X.pat, true);
-    const bool have_next = i < n_max;
-    double ca = 0.0, cb = 0.0, cc = 1.0;
-    if (sch.bounds && have_next) poly_coeffs(sch.p[i + 1], sch.alpha[i + 1], ca, cb, cc);
-    SquareOut so = square_step(c, X, m, mode, X.pool->prec, ca, cb, cc);
-    const double ei = std::sqrt(std::fmax(so.sums[0], 0.0));
-    const double trX = so.sums[1], trS = so.sums[2];
-    e.push_back(ei);
-    t.push_back(trX - trS);
-    trv.push_back(trX);
-    const double fl = so.sums[4] * 2.0 * B * B * B;
-    iflops.push_back(fl);
-    ksq.push_back(so.kernel_s);
-    alg_flops += fl;
-
-    // ---- stopping test (Algorithm 2) -----------------------------------------
-    // the criterion compares e_i with e_{i-2}: both must come from FP64 squares
-    bool stop = false;
-    const bool fp64_window = mode == M_F64 && (switch_iter >= 0 && i >= switch_iter + 2);
-    const bool low_window = low_to_end && mode != M_F64;
-    if (i >= 1 && (fp64_window || low_window)) {
-      if (i >= std::max(sch.n_min, 2) && p[i] != p[i - 1] && e[i] > C_STOP * e[i - 2] * e[i - 2]) {
-        stop = true;
-        stop_reason = SP2_STOP_CRITERION;
-      } else if (o.idem_stop > 0.0 && e[i] <= o.idem_stop) {
-        stop = true;
-        stop_reason = SP2_STOP_IDEMPOTENCY;
-      }
+// one iteration of Algorithm 2
+void Solver::iterate() {
+  auto t_it = std::chrono::steady_clock::now();
+  const int mode = X.pool->prec == P32 ? lowmode : M_F64;
+  if (tape) {
+    tape->it.emplace_back();
+    TapeIter &ti = tape->it.back();
+    ti.mask = clone_pattern(c, X.pat);
+    ti.mask.slot.reset();
+    ti.mode = mode;
+    ti.prec = X.pool->prec;
+    if (i >= 1) {
+      ti.p = p[i];
+      ti.alpha = alph[i];
+      poly_coeffs(p[i], alph[i], ti.ca, ti.cb, ti.cc);
     }
-    if (!stop && i == n_max) {
+    const int64_t ckb = X.pat.nnzb * (int64_t)BB * (X.pool->prec == P64 ? 8 : 4);
+    if (i % ck_every == 0 && (i == 0 || tape->bytes + ckb <= tape_budget)) add_checkpoint(c, *tape, i, X);
+  }
+  nnzbv.push_back(X.pat.nnzb);
+  max_nnzb = std::max(max_nnzb, X.pat.nnzb);
+  precv.push_back(mode == M_F64 ? SP2_PREC_FP64 : o.precision);
+
+  Maps m = build_maps(c, X.pat, true);
+  const bool have_next = i < n_max;
+  double ca = 0.0, cb = 0.0, cc = 1.0;
+  if (sch.bounds && have_next) poly_coeffs(sch.p[i + 1], sch.alpha[i + 1], ca, cb, cc);
+  SquareOut so = square_step(c, X, m, mode, X.pool->prec, ca, cb, cc);
+  const double ei = std::sqrt(std::fmax(so.sums[0], 0.0));
+  const double trX = so.sums[1], trS = so.sums[2];
+  e.push_back(ei);
+  t.push_back(trX - trS);
+  trv.push_back(trX);
+  const double fl = so.sums[4] * FL_BLOCK;
+  iflops.push_back(fl);
+  ksq.push_back(so.kernel_s);
+  alg_flops += fl;
+  last_flops = fl;
+
+  // ---- stopping test (Algorithm 2) -----------------------------------------
+  // the criterion compares e_i with e_{i-2}: both must come from FP64 squares
+  bool stop = false;
+  const bool fp64_window = mode == M_F64 && (switch_iter >= 0 && i >= switch_iter + 2);
+  const bool low_window = low_to_end && mode != M_F64;
+  if (i >= 1 && (fp64_window || low_window)) {
+    if (i >= std::max(sch.n_min, 2) && p[i] != p[i - 1] && e[i] > C_STOP * e[i - 2] * e[i - 2]) {
       stop = true;
-      stop_reason = SP2_STOP_NMAX;
-      status = SP2_WARN_NOT_CONVERGED;
+      stop_reason = SP2_STOP_CRITERION;
+    } else if (o.idem_stop > 0.0 && e[i] <= o.idem_stop) {
+      stop = true;
+      stop_reason = SP2_STOP_IDEMPOTENCY;
     }
-    if (stop) {
-      n = i;
-      c.sync();
-      itime.push_back(std::chrono::duration<double>(std::chrono::steady_clock::now() - t_it).count());
-      break;
-    }
-
-    // ---- next polynomial and truncation of X_{i+1} ----------------------------------
-    int pn;
-    double an;
-    if (sch.bounds) {
-      pn = sch.p[i + 1];
-      an = sch.alpha[i + 1];
-    } else {
-      pn = std::fabs(trS - (double)n_occ) < std::fabs(2.0 * trX - trS - (double)n_occ) ? 1 : 0;
-      an = 1.0;
-      poly_coeffs(pn, an, ca, cb, cc);
-      launch_update(c, X.pool->vals.p, X.pool->prec, m.idxmap.as<int32_t>(), X.pat.nbr,
-                    so.next.pat.row_of.as<int32_t>(), so.next.pat.col_idx.as<int32_t>(), so.next.pat.nnzb,
-                    so.next.pool->vals.p, so.next.pool->prec, ca, cb, cc, N, so.parts.as<double>());
-    }
-    p.push_back(pn);
-    alph.push_back(an);
-    if (corr) {
-      ct.it.emplace_back();
-      TapeIter &ti = ct.it.back();
-      ti.mask = clone_pattern(c, X.pat);
-      ti.mask.slot.reset();
-      ti.mode = mode;
-      ti.prec = X.pool->prec;
-      if (i >= 1) {
-        ti.p = p[i];
-        ti.alpha = alph[i];
-        poly_coeffs(p[i], alph[i], ti.ca, ti.cb, ti.cc);
-      }
-      const int64_t bytes = X.pat.nnzb * (int64_t)BB * (X.pool->prec == P64 ? 8 : 4);
-      if (i == 0 || (!seq_full && seq_bytes + bytes <= seq_budget)) {
-        add_checkpoint(c, ct, i, X);
-        seq_bytes += bytes;
-      } else {
-        seq_full = true;
-      }
-    }
-    DMat Xn = std::move(so.next);
-    const int64_t nout = Xn.pat.nnzb;
-    X = DMat{};  // X~_i is not needed any more: release it before X_{i+1} is compacted
-    {
-      Buf nrm2 = column(c, so.parts, nout, 3);
-      TruncResult tr = truncate_matrix(c, Xn, nrm2.as<double>(), sch.tau[i + 1], o.trunc_norm, o.coarse_bs);
-      errF.push_back(tr.err_frob);
-      errM.push_back(tr.err_mixed);
-      taus.push_back(sch.tau[i + 1]);
-    }
-    const bool to_fp64 = (o.switch_tol > 0.0 && ei < o.switch_tol) || (!low_to_end && ei < low_floor(mode, trX));
-    if (Xn.pool->prec == P32 && to_fp64) {
-      Xn = compact_values(c, Xn, P64);
-      sym_diag(c, Xn, 1.0);  // the FP64 tail starts from the symmetric part
-      switch_iter = i + 1;
-    } else {
-      Xn = compact_if_sparse(c, std::move(Xn));
-    }
-    X = std::move(Xn);
+  }
+  if (!stop && i == n_max) {
+    stop = true;
+    stop_reason = SP2_STOP_NMAX;
+    status = SP2_WARN_NOT_CONVERGED;
+  }
+  if (stop) {
+    n = i;
     c.sync();
-    itime.push_back(std::chrono::duration<double>(std::chrono::steady_clock::now() - t_it).count());
-    if (verbose())
-      std::fprintf(stderr, "[sp2] iter %d p=%d alpha=%.6f nnzb=%lld e=%.3e t=%.3e square %.1f ms (%.2f TFLOP/s)%s\n", i,
-                   p[i], alph[i], (long long)nnzbv[i], e[i], t[i], 1e3 * ksq[i],
-                   ksq[i] > 0.0 ? iflops[i] / ksq[i] / 1e12 : 0.0, mode == M_F64 ? "" : " low precision");
+    itime.push_back(seconds_since(t_it));
+    phase = corr ? CORRECT : FINISHED;
+    return;
   }
 
-  // ---- subspace correction ---------------------------------------------------------
-  CorrStats cs;
+  // ---- next polynomial and truncation of X_{i+1} ----------------------------------
+  int pn;
+  double an;
+  if (sch.bounds) {
+    pn = sch.p[i + 1];
+    an = sch.alpha[i + 1];
+  } else {
+    pn = std::fabs(trS - (double)n_occ) < std::fabs(2.0 * trX - trS - (double)n_occ) ? 1 : 0;
+    an = 1.0;
+    poly_coeffs(pn, an, ca, cb, cc);
+    launch_update(c, X.pool->vals.p, X.pool->prec, m.idxmap.as<int32_t>(), X.pat.nbr,
+                  so.next.pat.row_of.as<int32_t>(), so.next.pat.col_idx.as<int32_t>(), so.next.pat.nnzb,
+                  so.next.pool->vals.p, so.next.pool->prec, ca, cb, cc, N, so.parts.as<double>());
+  }
+  p.push_back(pn);
+  alph.push_back(an);
   if (corr) {
-    auto t_c = std::chrono::steady_clock::now();
-    X = subspace_correction(c, F, std::move(X), ct, n, p, alph, e, w, o, lowmode, taus[n], cs);
-    ct.it.clear();
+    ct.it.emplace_back();
+    TapeIter &ti = ct.it.back();
+    ti.mask = clone_pattern(c, X.pat);
+    ti.mask.slot.reset();
+    ti.mode = mode;
+    ti.prec = X.pool->prec;
+    if (i >= 1) {
+      ti.p = p[i];
+      ti.alpha = alph[i];
+      poly_coeffs(p[i], alph[i], ti.ca, ti.cb, ti.cc);
+    }
+    const int64_t bytes = X.pat.nnzb * (int64_t)BB * (X.pool->prec == P64 ? 8 : 4);
+    if (i == 0 || (!seq_full && seq_bytes + bytes <= seq_budget)) {
+      add_checkpoint(c, ct, i, X);
+      seq_bytes += bytes;
+    } else {
+      seq_full = true;
+    }
+  }
+  DMat Xn = std::move(so.next);
+  const int64_t nout = Xn.pat.nnzb;
+  X = DMat{};  // X~_i is not needed any more: release it before X_{i+1} is compacted
+  {
+    Buf nrm2 = column(c, so.parts, nout, 3);
+    TruncResult tr = truncate_matrix(c, Xn, nrm2.as<double>(), sch.tau[i + 1], o.trunc_norm, o.coarse_bs);
+    errF.push_back(tr.err_frob);
+    errM.push_back(tr.err_mixed);
+    taus.push_back(sch.tau[i + 1]);
+  }
+  const bool to_fp64 = (o.switch_tol > 0.0 && ei < o.switch_tol) || (!low_to_end && ei < low_floor(mode, trX));
+  if (Xn.pool->prec == P32 && to_fp64) {
+    Xn = compact_values(c, Xn, P64);
+    sym_diag(c, Xn, 1.0);  // the FP64 tail starts from the symmetric part
+    switch_iter = i + 1;
+  } else {
+    Xn = compact_if_sparse(c, std::move(Xn));
+  }
+  X = std::move(Xn);
+  c.sync();
+  itime.push_back(seconds_since(t_it));
+  if (verbose())
+    std::fprintf(stderr, "[sp2] iter %d p=%d alpha=%.6f nnzb=%lld e=%.3e t=%.3e square %.1f ms (%.2f TFLOP/s)%s\n", i,
+                 p[i], alph[i], (long long)nnzbv[i], e[i], t[i], 1e3 * ksq[i],
+                 ksq[i] > 0.0 ? iflops[i] / ksq[i] / 1e12 : 0.0, mode == M_F64 ? "" : " low precision");
+  ++i;
+}
+
+// One product of the occupied-subspace correction (the operation documented
+// with sp2_options.correct): Delta = [D, [D, F]], dD = J Delta along the
+// stored X~_0 .. X~_{n-1} (derivative of the polynomial steps, blocks dropped
+// within corr_tol), D <- FP64 purification of D + dD.  The commutator
+// C = [D, F] is formed in FP64 (it is small: the difference of two O(1)
+// products); [D, C] and the derivative steps use the arithmetic the expansion
+// used for each X~_i.
+void Solver::correct_step() {
+  const int lp = lowmode == M_F64 ? P64 : P32;
+  last_flops = 0.0;
+  switch (cstage) {
+    case C_COMM: {
+      if (cround == 0) {
+        // Once an iterate is close to a projector P (e_i small), the remaining
+        // derivative steps map dX to P dX (I - P) + (I - P) dX P plus parts
+        // inside the two subspaces, which the purification removes: they
+        // change the correction only at relative order e_i and are skipped.
+        n_deriv = n;
+        for (int k = 1; k < n; ++k)
+          if (e[k] < 1e-3) {
+            n_deriv = k;
+            break;
+          }
+        // the symmetric part of D: a low-precision iterate's diagonal blocks
+        // carry antisymmetric rounding noise, which the correction must not see
+        X = compact_values(c, X, X.pool->prec);
+        sym_diag(c, X, 1.0);
+      }
+      // C = D F - F D, antisymmetric, in FP64 arithmetic (stored in the low
+      // precision: the cancellation happens in the accumulators)
+      DMat D64 = as_prec(c, X, P64);
+      Maps mD = build_maps(c, D64.pat, true), mF = build_maps(c, F.pat, true);
+      PairOpt pc;
+      pc.neg2 = true;
+      pc.oprec = lp;
+      SquareOut co = pair_product(c, D64, mD, F, mF, pc);
+      last_flops = co.sums[4] * FL_BLOCK;
+      C = std::move(co.next);
+      sym_diag(c, C, -1.0);
+      drop(C, co);
+      if (verbose())
+        std::fprintf(stderr, "[sp2] correction: C = [D, F] nnzb=%lld square %.1f ms\n", (long long)C.pat.nnzb,
+                     1e3 * co.kernel_s);
+      cstage = C_DELTA;
+      break;
+    }
+    case C_DELTA: {
+      // dX~_0 = -(D C - C D) / w = -Delta / w
+      DMat Dl = as_prec(c, X, lp), Cl = as_prec(c, C, lp);
+      C = DMat();
+      Maps mD = build_maps(c, Dl.pat, true), mC = build_maps(c, Cl.pat, true);
+      PairOpt pd;
+      pd.neg2 = true;
+      pd.yanti = true;
+      pd.cc = -1.0 / w;
+      pd.mode = lowmode;
+      pd.oprec = lp;
+      SquareOut dd = pair_product(c, Dl, mD, Cl, mC, pd);
+      last_flops = dd.sums[4] * FL_BLOCK;
+      cs.delta_norm = std::sqrt(std::fmax(dd.sums[0], 0.0));  // no G: sums[0] = ||D C - C D||_F^2
+      dX = std::move(dd.next);
+      drop(dX, dd);
+      if (verbose())
+        std::fprintf(stderr, "[sp2] correction: Delta nnzb=%lld ||Delta||=%.3e product %.1f ms\n",
+                     (long long)dX.pat.nnzb, cs.delta_norm, 1e3 * dd.kernel_s);
+      ck = 0;
+      cstage = C_DERIV;
+      break;
+    }
+    case C_DERIV: {
+      // derivative of X_{k+1} = ca I + cb X~_k + cc X~_k^2 along dX~_k
+      const int k = ck;
+      Xi = ct.it[k].ckpt ? checkpoint_copy(ct, k) : replay_step(c, ct, k, Xi);
+      const int mi = Xi.pool->prec == P32 ? lowmode : M_F64;
+      DMat G = as_prec(c, dX, Xi.pool->prec);
+      Maps mX = build_maps(c, Xi.pat, true), mG = build_maps(c, G.pat, true);
+      double ca, cb, cc;
+      poly_coeffs(p[k + 1], alph[k + 1], ca, cb, cc);
+      PairOpt pj;
+      pj.G = &G;
+      pj.mg = &mG;
+      pj.cb = cb;
+      pj.cc = cc;
+      pj.mode = mi;
+      pj.oprec = Xi.pool->prec;
+      SquareOut jo = pair_product(c, Xi, mX, G, mG, pj);
+      last_flops = jo.sums[4] * FL_BLOCK;
+      dX = std::move(jo.next);
+      drop(dX, jo);
+      if (verbose())
+        std::fprintf(stderr, "[sp2] correction: derivative step %d/%d nnzb=%lld%s product %.1f ms\n", k + 1,
+                     n_deriv, (long long)dX.pat.nnzb, ct.it[k].ckpt ? "" : " (recomputed iterate)",
+                     1e3 * jo.kernel_s);
+      ++ck;
+      break;
+    }
+    case C_PURIFY: {
+      double ca, cb, cc;
+      poly_coeffs(ck % 2 == 0 ? 1 : 0, 1.0, ca, cb, cc);
+      Maps m = build_maps(c, X.pat, true);
+      SquareOut so = square_step(c, X, m, M_F64, P64, ca, cb, cc);
+      last_flops = so.sums[4] * FL_BLOCK;
+      cs.e_last = std::sqrt(std::fmax(so.sums[0], 0.0));
+      DMat Pn = std::move(so.next);
+      note(Pn);
+      Buf nrm2 = column(c, so.parts, Pn.pat.nnzb, 3);
+      truncate_matrix(c, Pn, nrm2.as<double>(), taus[n], o.trunc_norm, o.coarse_bs);
+      X = std::move(Pn);
+      if (verbose())
+        std::fprintf(stderr, "[sp2] correction: purification %d e=%.3e square %.1f ms\n", ck, cs.e_last,
+                     1e3 * so.kernel_s);
+      ++ck;
+      if (ck == o.corr_purify) {
+        cs.rounds++;
+        cround++;
+        cstage = C_COMM;
+        if (cround == o.correct) phase = FINISHED;
+      }
+      break;
+    }
+  }
+  if (cstage == C_DERIV && ck == n_deriv) {
+    // D + dD, then the purification
+    Xi = DMat();
+    cs.step_norm = frob_norm(c, dX);
+    X = add_union(c, X, 1.0, dX, 1.0);
+    dX = DMat();
+    note(X);
+    ck = 0;
+    cstage = C_PURIFY;
+  }
+  alg_flops += last_flops;
+  cs.flops += last_flops;
+}
+
+bool Solver::step() {
+  if (phase == FINISHED) fail(SP2_ERR_INVALID_ARG, "the expansion has finished: call sp2_density_end");
+  if (phase == FAILED) fail(SP2_ERR_INVALID_ARG, "an earlier step failed; release the solver");
+  auto t0 = std::chrono::steady_clock::now();
+  double ks0[3], kf0[3];
+  for (int m = 0; m < 3; ++m) {
+    ks0[m] = c.kern_s[m];
+    kf0[m] = c.kern_flops[m];
+  }
+  const bool expanding = phase == EXPAND;
+  const int it0 = i;
+  try {
+    if (expanding)
+      iterate();
+    else
+      correct_step();
     c.sync();
-    cs.time_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_c).count();
-    alg_flops += cs.flops;
+  } catch (...) {
+    phase = FAILED;
+    throw;
+  }
+  const double dt = seconds_since(t0);
+  busy_s += dt;
+  info = sp2_step_info{};
+  info.kind = expanding ? SP2_STEP_ITERATION : SP2_STEP_CORRECTION;
+  info.iteration = expanding ? it0 : -1;
+  info.flops = last_flops;
+  info.wall_s = dt;
+  int dom = 0;
+  for (int m = 0; m < 3; ++m) {
+    info.kernel_s[m] = c.kern_s[m] - ks0[m];
+    info.kernel_flops[m] = c.kern_flops[m] - kf0[m];
+    if (info.kernel_flops[m] > info.kernel_flops[dom]) dom = m;
+  }
+  info.precision = dom == M_F64 ? SP2_PREC_FP64 : (dom == M_F32 ? SP2_PREC_FP32 : SP2_PREC_BF16X3);
+  if (phase == CORRECT || (phase == FINISHED && corr)) cs.time_s += dt;
+  if (phase == FINISHED && corr) {
+    ct.it.clear();
     if (verbose())
       std::fprintf(stderr, "[sp2] correction: %d round(s) %.3f s ||Delta||=%.3e ||dD||=%.3e e_last=%.3e\n", cs.rounds,
                    cs.time_s, cs.delta_norm, cs.step_norm, cs.e_last);
   }
+  info.done = phase == FINISHED ? 1 : 0;
+  return phase == FINISHED;
+}
 
+int Solver::finish(sp2_bsr **D_out, double *hest, double *lest, sp2_stats *st, sp2_tape **tape_out) {
+  if (phase != FINISHED) fail(SP2_ERR_INVALID_ARG, "the expansion has not finished");
+  auto t0 = std::chrono::steady_clock::now();
   // ---- Step 3 and outputs ---------------------------------------------------------
   double h = NaN, l = NaN;
   {
     std::vector<double> unit(n + 1);
-    for (int i = 0; i <= n; ++i)
-      unit[i] = precv[i] == SP2_PREC_FP64 ? DELTA_N
-                : (precv[i] == SP2_PREC_FP32 ? 1.0 / 16777216.0 : 1.0 / 65536.0);
+    for (int k = 0; k <= n; ++k)
+      unit[k] = precv[k] == SP2_PREC_FP64 ? DELTA_N : (precv[k] == SP2_PREC_FP32 ? 1.0 / 16777216.0 : 1.0 / 65536.0);
     homo_lumo(sch, e, trv, p, alph, n, lmin, lmax, N, n_occ, h, l, &unit);
   }
   double bound = NaN;
   if (sch.bounds) {
     bound = 0.0;
-    for (int i = 0; i <= n; ++i)
-      if (errM[i] > 0.0) bound += errM[i] / (sch.xi[i] - errM[i]);
+    for (int k = 0; k <= n; ++k)
+      if (errM[k] > 0.0) bound += errM[k] / (sch.xi[k] - errM[k]);
   }
   if (status == SP2_OK && std::fabs(trv[n] - (double)n_occ) > 0.5) status = SP2_WARN_TRACE;
   if (X.pool->prec == P32) {  // a low-precision result: return its symmetric part
@@ -1046,7 +1157,8 @@ int run_density(Ctx &c, const sp2_bsr *Fin, int64_t n_occ, double lmin, double l
     sym_diag(c, X, 1.0);
   }
   *D_out = export_bsr(c, X);
-  const double elapsed = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+  X = DMat();
+  busy_s += seconds_since(t0);
   if (hest) *hest = h;
   if (lest) *lest = l;
   if (st) {
@@ -1058,11 +1170,11 @@ int run_density(Ctx &c, const sp2_bsr *Fin, int64_t n_occ, double lmin, double l
     st->homo_ub_est = h;
     st->lumo_lb_est = l;
     st->subspace_err_bound = bound;
-    st->time_s = elapsed;
+    st->time_s = busy_s;
     st->alg_flops = alg_flops;
     st->max_nnzb = max_nnzb;
     st->square_time_total_s = 0.0;
-    for (int i = 0; i <= n; ++i) st->square_time_total_s += ksq[i];
+    for (int k = 0; k <= n; ++k) st->square_time_total_s += ksq[k];
     st->corr_rounds = cs.rounds;
     st->corr_time_s = cs.time_s;
     st->corr_flops = cs.flops;
@@ -1072,29 +1184,58 @@ int run_density(Ctx &c, const sp2_bsr *Fin, int64_t n_occ, double lmin, double l
     st->corr_max_nnzb = cs.max_nnzb;
     st->seq_bytes = seq_bytes;
     st->device_peak_bytes = (int64_t)c.peak_bytes;
-    for (int i = 0; i <= n; ++i) {
-      if (st->square_time_s) st->square_time_s[i] = ksq[i];
-      if (st->e) st->e[i] = e[i];
-      if (st->t) st->t[i] = t[i];
-      if (st->trace) st->trace[i] = trv[i];
-      if (st->alpha) st->alpha[i] = alph[i];
-      if (st->tau) st->tau[i] = taus[i];
-      if (st->trunc_err_frob) st->trunc_err_frob[i] = errF[i];
-      if (st->trunc_err_mixed) st->trunc_err_mixed[i] = errM[i];
-      if (st->iter_time_s) st->iter_time_s[i] = itime[i];
-      if (st->iter_flops) st->iter_flops[i] = iflops[i];
-      if (st->p) st->p[i] = p[i];
-      if (st->precision) st->precision[i] = precv[i];
-      if (st->nnzb) st->nnzb[i] = nnzbv[i];
+    for (int k = 0; k <= n; ++k) {
+      if (st->square_time_s) st->square_time_s[k] = ksq[k];
+      if (st->e) st->e[k] = e[k];
+      if (st->t) st->t[k] = t[k];
+      if (st->trace) st->trace[k] = trv[k];
+      if (st->alpha) st->alpha[k] = alph[k];
+      if (st->tau) st->tau[k] = taus[k];
+      if (st->trunc_err_frob) st->trunc_err_frob[k] = errF[k];
+      if (st->trunc_err_mixed) st->trunc_err_mixed[k] = errM[k];
+      if (st->iter_time_s) st->iter_time_s[k] = itime[k];
+      if (st->iter_flops) st->iter_flops[k] = iflops[k];
+      if (st->p) st->p[k] = p[k];
+      if (st->precision) st->precision[k] = precv[k];
+      if (st->nnzb) st->nnzb[k] = nnzbv[k];
     }
   }
-  if (tape) {
+  if (tape && tape_out) {
     tape->n_iter = n;
     tape->it.resize(n + 1);
     *tape_out = tape.release();
   }
   return status;
 }
+
+int run_density(Ctx &c, const sp2_bsr *Fin, int64_t n_occ, double lmin, double lmax, const double *hub,
+                const double *llb, const sp2_options &o, sp2_bsr **D_out, double *hest, double *lest,
+                sp2_stats *st, sp2_tape **tape_out) {
+  if (!D_out) fail(SP2_ERR_INVALID_ARG, "D_out is NULL");
+  *D_out = nullptr;
+  if (tape_out) *tape_out = nullptr;
+  if (st && st->capacity < o.n_max_cap + 1) fail(SP2_ERR_INVALID_ARG, "stats capacity < n_max_cap + 1");
+  if (tape_out && !o.record_tape) fail(SP2_ERR_INVALID_ARG, "a tape needs record_tape = 1");
+  Solver s(c);
+  s.begin(Fin, n_occ, lmin, lmax, hub, llb, o);
+  while (!s.step()) {
+  }
+  return s.finish(D_out, hest, lest, st, tape_out);
+}
+
+}  // namespace
+
+struct SolverHandle {
+  Ctx *ctx = nullptr;
+  std::unique_ptr<Solver> s;
+};
+
+}  // namespace sp2
+
+struct sp2_solver : public sp2::SolverHandle {};
+
+namespace sp2 {
+namespace {
 
 // ---------------------------------------------------------------- adjoint
 // X~_{i} from X~_{i-1} with the recorded polynomial and mask (frozen map)
@@ -1351,6 +1492,56 @@ int sp2_density(sp2_ctx *ctx, const sp2_bsr *F, int64_t n_occ, double lmin, doub
       sp2_options_default(&o);
     return run_density(*ctx, F, n_occ, lmin, lmax, homo_ub, lumo_lb, o, D_out, homo_est, lumo_est, stats, tape);
   });
+}
+
+int sp2_density_begin(sp2_ctx *ctx, const sp2_bsr *F, int64_t n_occ, double lmin, double lmax,
+                      const double *homo_ub, const double *lumo_lb, const sp2_options *opt, sp2_solver **solver) {
+  return guarded(ctx, [&]() {
+    if (!solver) fail(SP2_ERR_INVALID_ARG, "solver is NULL");
+    *solver = nullptr;
+    sp2_options o;
+    if (opt)
+      o = *opt;
+    else
+      sp2_options_default(&o);
+    std::unique_ptr<sp2_solver> h(new sp2_solver());
+    h->ctx = ctx;
+    h->s.reset(new Solver(*ctx));
+    h->s->begin(F, n_occ, lmin, lmax, homo_ub, lumo_lb, o);
+    *solver = h.release();
+    return SP2_OK;
+  });
+}
+
+int sp2_density_step(sp2_ctx *ctx, sp2_solver *solver, sp2_step_info *info) {
+  return guarded(ctx, [&]() {
+    if (!solver || !solver->s) fail(SP2_ERR_INVALID_ARG, "solver is NULL");
+    if (solver->ctx != ctx) fail(SP2_ERR_INVALID_ARG, "solver belongs to another context");
+    solver->s->step();
+    if (info) *info = solver->s->info;
+    return SP2_OK;
+  });
+}
+
+int sp2_density_end(sp2_ctx *ctx, sp2_solver *solver, sp2_bsr **D_out, double *homo_est, double *lumo_est,
+                    sp2_stats *stats, sp2_tape **tape) {
+  return guarded(ctx, [&]() {
+    if (!solver || !solver->s) fail(SP2_ERR_INVALID_ARG, "solver is NULL");
+    if (solver->ctx != ctx) fail(SP2_ERR_INVALID_ARG, "solver belongs to another context");
+    if (!D_out) fail(SP2_ERR_INVALID_ARG, "D_out is NULL");
+    *D_out = nullptr;
+    if (tape) *tape = nullptr;
+    Solver &s = *solver->s;
+    if (stats && stats->capacity < s.o.n_max_cap + 1) fail(SP2_ERR_INVALID_ARG, "stats capacity < n_max_cap + 1");
+    if (tape && !s.o.record_tape) fail(SP2_ERR_INVALID_ARG, "a tape needs record_tape = 1");
+    return s.finish(D_out, homo_est, lumo_est, stats, tape);
+  });
+}
+
+void sp2_solver_free(sp2_ctx *ctx, sp2_solver *solver) {
+  if (!solver) return;
+  if (ctx) (void)hipSetDevice(ctx->device);
+  delete solver;
 }
 
 int sp2_vjp(sp2_ctx *ctx, const sp2_tape *tape, const sp2_bsr *W, sp2_bsr **Fbar_out) {

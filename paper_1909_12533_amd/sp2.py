@@ -18,6 +18,7 @@ import torch
 from . import _lib as L
 
 _PREC = {"fp64": L.PREC_FP64, "fp32": L.PREC_FP32, "bf16x3": L.PREC_BF16X3}
+_PREC_NAME = {v: k for k, v in _PREC.items()}
 _NORM = {"none": L.TRUNC_NONE, "frob": L.TRUNC_FROB, "frobinf": L.TRUNC_FROBINF}
 _STOP = {L.STOP_CRITERION: "criterion", L.STOP_IDEMPOTENCY: "idempotency", L.STOP_NMAX: "n_max", 0: ""}
 
@@ -316,51 +317,123 @@ class Tape:
             pass
 
 
+class _Stats:
+    """Host arrays of an sp2_stats record and the DensityResult built from it."""
+
+    _DOUBLE = ("e", "t", "trace", "alpha", "tau", "trunc_err_frob", "trunc_err_mixed", "iter_time_s", "iter_flops",
+               "square_time_s")
+
+    def __init__(self, n_max_cap):
+        cap = int(n_max_cap) + 1
+        self.arr = {k: np.zeros(cap) for k in self._DOUBLE}
+        self.arr_p = np.zeros(cap, dtype=np.int32)
+        self.arr_prec = np.zeros(cap, dtype=np.int32)
+        self.arr_nnzb = np.zeros(cap, dtype=np.int64)
+        st = L.sp2_stats()
+        st.capacity = cap
+        for k, a in self.arr.items():
+            setattr(st, k, a.ctypes.data_as(C.POINTER(C.c_double)))
+        st.p = self.arr_p.ctypes.data_as(C.POINTER(C.c_int32))
+        st.precision = self.arr_prec.ctypes.data_as(C.POINTER(C.c_int32))
+        st.nnzb = self.arr_nnzb.ctypes.data_as(C.POINTER(C.c_int64))
+        self.st = st
+
+    def result(self, ctx, rc, D, he, le, tape_h, record_tape):
+        st = self.st
+        n = int(st.n_iter)
+        iters = {k: a[: n + 1].copy() for k, a in self.arr.items()}
+        iters["p"] = self.arr_p[: n + 1].copy()
+        iters["precision"] = self.arr_prec[: n + 1].copy()
+        iters["nnzb"] = self.arr_nnzb[: n + 1].copy()
+        return DensityResult(D=D, status=rc, homo_est=he, lumo_est=le, n_iter=n, n_max=int(st.n_max),
+                             n_min=int(st.n_min), stop_reason=_STOP.get(int(st.stop_reason), "?"),
+                             switch_iter=int(st.switch_iter), subspace_err_bound=float(st.subspace_err_bound),
+                             time_s=float(st.time_s), alg_flops=float(st.alg_flops), max_nnzb=int(st.max_nnzb),
+                             square_time_s=float(st.square_time_total_s),
+                             correction={k: getattr(st, k) for k in ("corr_rounds", "corr_time_s", "corr_flops",
+                                                                     "corr_delta_norm", "corr_step_norm",
+                                                                     "corr_e_last", "corr_max_nnzb", "seq_bytes",
+                                                                     "device_peak_bytes")},
+                             iters=iters, tape=Tape(ctx, tape_h) if record_tape else None)
+
+
+def _bounds(homo_ub, lumo_lb):
+    hub = C.byref(C.c_double(homo_ub)) if homo_ub is not None else None
+    llb = C.byref(C.c_double(lumo_lb)) if lumo_lb is not None else None
+    return hub, llb
+
+
 def density(F: BsrMatrix, n_occ: int, lmin: float, lmax: float, homo_ub=None, lumo_lb=None,
             ctx: Context | None = None, **opts) -> DensityResult:
     """D = theta(mu I - F) by SP2 / SP2ACC; see sp2_density in sp2dm.h."""
     ctx = ctx or context(F.device.index)
     o = options(**opts)
-    cap = int(o.n_max_cap) + 1
-    arr = {k: np.zeros(cap) for k in ("e", "t", "trace", "alpha", "tau", "trunc_err_frob", "trunc_err_mixed",
-                                      "iter_time_s", "iter_flops", "square_time_s")}
-    arr_p = np.zeros(cap, dtype=np.int32)
-    arr_prec = np.zeros(cap, dtype=np.int32)
-    arr_nnzb = np.zeros(cap, dtype=np.int64)
-    st = L.sp2_stats()
-    st.capacity = cap
-    for k, a in arr.items():
-        setattr(st, k, a.ctypes.data_as(C.POINTER(C.c_double)))
-    st.p = arr_p.ctypes.data_as(C.POINTER(C.c_int32))
-    st.precision = arr_prec.ctypes.data_as(C.POINTER(C.c_int32))
-    st.nnzb = arr_nnzb.ctypes.data_as(C.POINTER(C.c_int64))
-    hub = C.byref(C.c_double(homo_ub)) if homo_ub is not None else None
-    llb = C.byref(C.c_double(lumo_lb)) if lumo_lb is not None else None
+    sts = _Stats(o.n_max_cap)
+    hub, llb = _bounds(homo_ub, lumo_lb)
     out = C.POINTER(L.sp2_bsr)()
     he, le = C.c_double(), C.c_double()
     tape_h = C.c_void_p()
     s = F._struct()
     rc = ctx.lib.sp2_density(ctx.h, C.byref(s), int(n_occ), float(lmin), float(lmax), hub, llb, C.byref(o),
-                             C.byref(out), C.byref(he), C.byref(le), C.byref(st),
+                             C.byref(out), C.byref(he), C.byref(le), C.byref(sts.st),
                              C.byref(tape_h) if o.record_tape else None)
     ctx._check(rc)
     D = ctx.take(out)
     ctx.trim()
-    n = int(st.n_iter)
-    iters = {k: a[: n + 1].copy() for k, a in arr.items()}
-    iters["p"] = arr_p[: n + 1].copy()
-    iters["precision"] = arr_prec[: n + 1].copy()
-    iters["nnzb"] = arr_nnzb[: n + 1].copy()
-    return DensityResult(D=D, status=rc, homo_est=he.value, lumo_est=le.value, n_iter=n, n_max=int(st.n_max),
-                         n_min=int(st.n_min), stop_reason=_STOP.get(int(st.stop_reason), "?"),
-                         switch_iter=int(st.switch_iter), subspace_err_bound=float(st.subspace_err_bound),
-                         time_s=float(st.time_s), alg_flops=float(st.alg_flops), max_nnzb=int(st.max_nnzb),
-                         square_time_s=float(st.square_time_total_s),
-                         correction={k: getattr(st, k) for k in ("corr_rounds", "corr_time_s", "corr_flops",
-                                                                 "corr_delta_norm", "corr_step_norm", "corr_e_last",
-                                                                 "corr_max_nnzb", "seq_bytes",
-                                                                 "device_peak_bytes")},
-                         iters=iters, tape=Tape(ctx, tape_h) if o.record_tape else None)
+    return sts.result(ctx, rc, D, he.value, le.value, tape_h, o.record_tape)
+
+
+class Solver:
+    """The expansion one unit of work at a time (sp2_density_begin / _step /
+    _end in sp2dm.h): ``step()`` runs one iteration of Algorithm 2, or one
+    product of the subspace correction."""
+
+    def __init__(self, F: BsrMatrix, n_occ: int, lmin: float, lmax: float, homo_ub=None, lumo_lb=None,
+                 ctx: Context | None = None, **opts):
+        self.ctx = ctx or context(F.device.index)
+        self.F = F  # borrowed by the library until end()
+        self.o = options(**opts)
+        self._s = F._struct()
+        hub, llb = _bounds(homo_ub, lumo_lb)
+        self.h = C.c_void_p()
+        self.ctx._check(self.ctx.lib.sp2_density_begin(self.ctx.h, C.byref(self._s), int(n_occ), float(lmin),
+                                                       float(lmax), hub, llb, C.byref(self.o), C.byref(self.h)))
+        self.done = False
+
+    def step(self) -> dict:
+        """One step; returns its sp2_step_info as a dict (done, kind, iteration,
+        precision, flops, wall_s, kernel_s[3], kernel_flops[3])."""
+        info = L.sp2_step_info()
+        self.ctx._check(self.ctx.lib.sp2_density_step(self.ctx.h, self.h, C.byref(info)))
+        self.done = bool(info.done)
+        return {"done": self.done, "kind": {L.STEP_ITERATION: "iteration", L.STEP_CORRECTION: "correction"}[info.kind],
+                "iteration": int(info.iteration), "precision": _PREC_NAME[int(info.precision)],
+                "flops": float(info.flops), "wall_s": float(info.wall_s), "kernel_s": list(info.kernel_s),
+                "kernel_flops": list(info.kernel_flops)}
+
+    def end(self) -> DensityResult:
+        sts = _Stats(self.o.n_max_cap)
+        out = C.POINTER(L.sp2_bsr)()
+        he, le = C.c_double(), C.c_double()
+        tape_h = C.c_void_p()
+        rc = self.ctx.lib.sp2_density_end(self.ctx.h, self.h, C.byref(out), C.byref(he), C.byref(le),
+                                          C.byref(sts.st), C.byref(tape_h) if self.o.record_tape else None)
+        self.ctx._check(rc)
+        D = self.ctx.take(out)
+        self.free()
+        self.ctx.trim()
+        return sts.result(self.ctx, rc, D, he.value, le.value, tape_h, self.o.record_tape)
+
+    def free(self):
+        if self.h:
+            self.ctx.lib.sp2_solver_free(self.ctx.h, self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
 
 
 def square_step(X: BsrMatrix, a: float, b: float, c: float, precision="fp64", ctx: Context | None = None):

@@ -211,3 +211,55 @@ def test_low_precision_to_the_end(gpu_lib):
     assert not np.isnan(r.homo_est) and not np.isnan(r.lumo_est)
     assert homo <= r.homo_est + 1e-9 and r.lumo_est - 1e-9 <= lumo
     assert r.homo_est < r.lumo_est
+
+
+@pytest.mark.parametrize("prec,correct", [("fp64", 0), ("bf16x3", 0), ("bf16x3", 1)])
+def test_stepped_solver_equals_density(gpu_lib, prec, correct):
+    """sp2_density_begin / _step / _end do the work of sp2_density: bit-identical
+    D, the same statistics, one step per iteration of Algorithm 2 plus one per
+    product of the correction, and step flops summing to the run's."""
+    import torch
+
+    sp2 = gpu_lib
+    Fh, info = lattice_fock(8, seed=0)
+    Fd = bsr_to_dense(Fh)
+    no = info["n_occ"]
+    lmin, lmax = O.gershgorin_bounds(Fd)
+    opts = dict(accel=True, trunc_norm="frobinf", tau_fixed=1e-5, coarse_bs=512, precision=prec, correct=correct,
+                switch_tol=0.0 if correct else 1e-3)
+    F = sp2.BsrMatrix.from_host(Fh)
+    ref = sp2.density(F, no, lmin, lmax, -0.31, 0.33, **opts)
+    s = sp2.Solver(F, no, lmin, lmax, -0.31, 0.33, **opts)
+    steps, flops = 0, 0.0
+    done = False
+    kinds = []
+    while not done:
+        st = s.step()
+        done = st["done"]
+        steps += 1
+        flops += st["flops"]
+        kinds.append(st["kind"])
+        assert st["wall_s"] > 0.0
+        if st["kind"] == "iteration":
+            assert st["iteration"] == steps - 1
+            k = {"fp64": 0, "fp32": 1, "bf16x3": 2}[st["precision"]]
+            assert st["kernel_flops"][k] == pytest.approx(st["flops"], rel=1e-12)
+            assert st["kernel_s"][k] > 0.0
+    r = s.end()
+    with pytest.raises(sp2.Sp2Error):
+        s2 = sp2.Solver(F, no, lmin, lmax, -0.31, 0.33, **opts)
+        s2.end()  # before the expansion finished
+    print(f"{prec} correct={correct}: {steps} steps, n={r.n_iter}, flops {flops:.4e} vs {ref.alg_flops:.4e}")
+    assert torch.equal(r.D.row_ptr, ref.D.row_ptr) and torch.equal(r.D.col_idx, ref.D.col_idx)
+    assert torch.equal(r.D.val, ref.D.val)
+    assert r.n_iter == ref.n_iter and r.stop_reason == ref.stop_reason and r.status == ref.status
+    assert np.array_equal(r.iters["e"], ref.iters["e"])
+    assert flops == pytest.approx(ref.alg_flops, rel=1e-12)
+    assert r.alg_flops == ref.alg_flops
+    n_corr = 0
+    if correct:
+        assert r.correction["corr_rounds"] == 1
+        n_corr = steps - (r.n_iter + 1)
+        assert n_corr >= 3  # commutator, Delta, purification (and the derivative steps)
+    assert steps == r.n_iter + 1 + n_corr
+    assert kinds == ["iteration"] * (r.n_iter + 1) + ["correction"] * n_corr
