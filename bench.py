@@ -1,19 +1,28 @@
 """Benchmark of the SP2 / SP2ACC density-matrix hot path on one MI355X.
 
-One step = one full density-matrix expansion (Step 1 schedule, Algorithm 1,
-Algorithm 2 with truncation and stopping, Step 3 homo/lumo estimates) of the
-workload's Fock matrix, already resident in HBM, through the C ABI.  The
-workload is the tight-binding Fock matrix on a 20 x 20 x 20 lattice with 4
-basis functions per atom (N = 32,000), FP64 SP2ACC with 64 x 64 leaf blocks,
-tau = 1e-6 (Frob-Inf truncation, 4096 submatrices), Gershgorin spectral
-bounds, homo/lumo bounds from a trace-correcting first run (untimed), as in
-the two-run protocol of the paper's "Numerical experiments" section.
+Workload (default): the tight-binding Fock matrix on a 30 x 30 x 30 lattice
+with 4 basis functions per atom (N = 108,000), SP2ACC with 64 x 64 leaf
+blocks, tau = 1e-6 (Frob-Inf truncation, 4096 submatrices), Gershgorin
+spectral bounds, homo/lumo bounds from the trace-correcting first run of the
+two-run protocol of the paper's "Numerical experiments" section (its result
+is recorded in bench_run1.json).  The timed path is the mixed-precision one:
+BF16x3 squares to the expansion's own stopping criterion, then the FP64
+occupied-subspace correction; the plain FP64 expansion of the same input is
+run once beside it as the reference (time to D and ||D - D_FP64||_F).
 
-Prints one JSON line: block-sparse TFLOP/s (algorithmic flops
-2 * 64^3 * #{(I,K,J): I <= J, X~_IK != 0 != X~_KJ} summed over the squares,
-divided by the time to D), the time to D, the roofline of the MFMA square
-kernel (device time from HIP events on the stream it runs on), and the CPU
-oracle timed on a bounded sample.
+One step = one unit of the stepped C ABI (sp2_density_step): one iteration
+of Algorithm 2 (planning, MFMA square with the fused update, e_i and t_i,
+the stopping test, truncation) or one block product of the correction; the
+first step of a solve also runs Step 1 and Algorithm 1, its last Step 3 and
+the export of D.  Solves run back to back; W untimed steps, then K timed
+steps; every step is synchronized and timed on its own, so the time to D of
+a solve is the sum of its steps.  Inputs are resident in HBM before timing.
+
+Prints one JSON line: value = block-sparse TFLOP/s of a solve (the
+expansion's algorithmic flops 2 * 64^3 * #{(I,K,J): I <= J, X~_IK != 0 !=
+X~_KJ} over its time to D), the time to D, the roofline of the dominant MFMA
+kernel over the timed steps (device time from HIP events on the stream it
+runs on), the FP64 reference and the CPU oracle timed on a bounded sample.
 """
 from __future__ import annotations
 
@@ -30,9 +39,9 @@ sys.path.insert(0, ROOT)
 PEAK = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0 / 3.0}  # dense MFMA TFLOP/s (algorithmic for bf16x3)
 
 CONFIGS = {
-    "c1": dict(L=20, tau=1e-6, precision="fp64"),
-    "c2": dict(L=30, tau=1e-6, precision="fp32"),
-    "c4": dict(L=40, tau=1e-5, precision="fp32"),
+    "c1": dict(L=20, tau=1e-6),
+    "c2": dict(L=30, tau=1e-6),
+    "c4": dict(L=40, tau=1e-5),
 }
 
 
@@ -61,7 +70,8 @@ def cpu_baseline(L=12, tau=1e-6):
     t0 = time.perf_counter()
     r = O.sp2(Fd, no, lmin, lmax, h, lu, accel=True, trunc_norm=O.TRUNC_FROBINF, tau_fixed=tau, coarse_bs=4096)
     dt = time.perf_counter() - t0
-    threads = max([p.get("num_threads", 1) for p in threadpool_info() if p.get("user_api") == "blas"] or [1])
+    blas = [p for p in threadpool_info() if p.get("user_api") == "blas"]
+    threads = max([p.get("num_threads", 1) for p in blas] or [1])
     return {
         "value": r.alg_flops / dt / 1e12,
         "unit": "TFLOP/s",
@@ -69,6 +79,8 @@ def cpu_baseline(L=12, tau=1e-6):
         "kind": "oracle",
         "sample": f"one SP2ACC run (tau={tau}, Frob-Inf) of the {L}x{L}x{L}x4 lattice, N={info['n']}, "
                   f"n={r.n} iterations, {dt:.1f} s, algorithmic block-sparse flops / wall time",
+        "host_cpu_count": os.cpu_count(),
+        "blas": [f"{p.get('internal_api')} {p.get('version')} ({p.get('num_threads')} threads)" for p in blas],
     }
 
 
@@ -130,12 +142,21 @@ def bsr_diff_frobenius(A, B):
     hit = kb[pos] == ka
     wa = torch.where(ra == ca, 1.0, 2.0).double()
     wb = torch.where(rb == cb, 1.0, 2.0).double()
-    d = A.val.clone()
-    d[hit] -= B.val[pos[hit]]
-    tot = (wa * (d * d).sum(dim=(1, 2))).sum()
+    tot = torch.zeros((), dtype=torch.float64, device=A.val.device)
+    chunk = 1 << 16  # blocks per pass (2 GB of FP64 differences)
+    for a in range(0, ka.numel(), chunk):
+        sl = slice(a, a + chunk)
+        d = A.val[sl].clone()
+        h = hit[sl]
+        d[h] -= B.val[pos[sl][h]]
+        tot += (wa[sl] * (d * d).sum(dim=(1, 2))).sum()
+        del d
     used = torch.zeros(kb.numel(), dtype=torch.bool, device=kb.device)
     used[pos[hit]] = True
-    tot += (wb[~used] * (B.val[~used] ** 2).sum(dim=(1, 2))).sum()
+    rest = torch.nonzero(~used).flatten()
+    for a in range(0, rest.numel(), chunk):
+        idx = rest[a:a + chunk]
+        tot += (wb[idx] * (B.val[idx] ** 2).sum(dim=(1, 2))).sum()
     return float(tot.sqrt())
 
 
@@ -288,13 +309,94 @@ def norm_study(sp2, sizes, half_bw=300, coarse=(128, 512)):
     return out
 
 
+def stepped_run(sp2, F, no, lmin, lmax, hub, llb, opts, warmup, steps):
+    """Solves of the workload, one after the other, run step by step through
+    the stepped C ABI (one step = one iteration of Algorithm 2 or one product
+    of the subspace correction; the first step of a solve includes Step 1 and
+    Algorithm 1, its last Step 3 and the export of D).  ``warmup`` untimed
+    steps, then exactly ``steps`` timed ones between two synchronizations;
+    the first solve is then run to its end if it has not finished.  Every step
+    is timed on its own (synchronized before and after), so the time to D of
+    the first solve is the sum of its steps."""
+    import torch
+
+    recs, first = [], None
+    st = {"solver": None, "solve": -1}
+
+    def one(phase):
+        nonlocal first
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        if st["solver"] is None:
+            st["solver"] = sp2.Solver(F, no, lmin, lmax, hub, llb, **opts)
+            st["solve"] += 1
+        info = st["solver"].step()
+        res = None
+        if info["done"]:
+            res = st["solver"].end()
+            st["solver"] = None
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        info.update(solve=st["solve"], wall=dt, phase=phase)
+        recs.append(info)
+        if res is not None and first is None:
+            first = res
+        bf = info["kernel_flops"][2] / max(info["kernel_s"][2], 1e-30) / 1e12 if info["kernel_s"][2] > 0 else 0.0
+        log(f"{phase} step {len(recs) - 1:3d}: solve {info['solve']} {info['kind']:10s} it {info['iteration']:3d} "
+            f"{info['precision']:6s} {dt:8.3f} s  {info['flops'] / 1e12:9.2f} TF"
+            + (f"  bf16x3 kernels {bf:6.1f} TF/s" if bf else "") + ("  [solve done]" if info["done"] else ""))
+
+    for _ in range(warmup):
+        one("warmup")
+    torch.cuda.synchronize()
+    t_a = time.perf_counter()
+    for _ in range(steps):
+        one("timed")
+    torch.cuda.synchronize()
+    t_b = time.perf_counter()
+    while first is None:
+        one("finish")
+    if st["solver"] is not None:
+        st["solver"].free()
+        st["solver"] = None
+    return recs, first, t_b - t_a
+
+
+def trace_of(D):
+    """tr D from the diagonal blocks (the first block of each block row when
+    present), on the device."""
+    import torch
+
+    first = D.row_ptr[:-1]
+    has = first < D.row_ptr[1:]
+    rows = torch.arange(D.nbr, device=D.device)[has]
+    dpos = first[has]
+    dpos = dpos[D.col_idx[dpos].to(torch.int64) == rows]
+    return float(torch.diagonal(D.val[dpos], dim1=1, dim2=2).sum())
+
+
+def run1_bounds(config, L, tau):
+    """Committed run-1 estimates of this workload (None when absent)."""
+    path = os.path.join(ROOT, "bench_run1.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        d = json.load(fh)
+    r = d.get(config)
+    if not r or r.get("L") != L or r.get("tau") != tau:
+        return None
+    return r["homo_ub"], r["lumo_lb"]
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", default="c1", choices=sorted(CONFIGS))
-    ap.add_argument("--precision", default=None, choices=["fp64", "fp32", "bf16x3"])
+    ap.add_argument("--steps", type=int, default=20, help="timed steps (one step: an iteration of Algorithm 2 or a "
+                                                          "product of the subspace correction)")
+    ap.add_argument("--warmup", type=int, default=5, help="untimed steps before the timed ones")
+    ap.add_argument("--config", default="c2", choices=sorted(CONFIGS))
+    ap.add_argument("--precision", default="bf16x3", choices=["fp64", "fp32", "bf16x3"],
+                    help="arithmetic of the bulk squares of the timed path (default: BF16x3 with the correction)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="copy a buffer of this size once before timing (reference for HBM traffic counters)")
@@ -302,10 +404,13 @@ def main():
                     help="subspace-correction rounds (default: 0 for fp64, 1 for fp32 / bf16x3)")
     ap.add_argument("--corr-tol", type=float, default=None,
                     help="Frobenius budget for dropping blocks of the correction's intermediates (library default)")
+    ap.add_argument("--corr-purify", type=int, default=None, help="purification steps per correction round")
+    ap.add_argument("--corr-mcweeny", type=int, default=1,
+                    help="1 (default): purify with one McWeeny step (an FP64 square and a low-precision product); "
+                         "0: FP64 squares X^2, 2X - X^2")
+    ap.add_argument("--corr-deriv-tol", type=float, default=None, help="derivative steps stop below this e_k")
     ap.add_argument("--no-reference", action="store_true",
                     help="with a low --precision: skip the FP64 reference run (largest workloads)")
-    ap.add_argument("--compare", default="bf16x3", choices=["none", "fp32", "bf16x3"],
-                    help="with --precision fp64: one mixed run (with and without the correction) for speedup / error")
     ap.add_argument("--adjoint", action="store_true",
                     help="instead of the expansion benchmark: JVP and VJP of tr(W D) in FP64 and mixed precision")
     ap.add_argument("--adjoint-runs", default="fp64,fp32,bf16x3,bf16x3/fp32",
@@ -323,13 +428,15 @@ def main():
                     help="stop after this many iterations (a capped run of a workload too long for one call)")
     ap.add_argument("--bounds", default=None,
                     help="homo_ub,lumo_lb known in advance (e.g. from a previous SCF cycle): skips the first run")
+    ap.add_argument("--run1", action="store_true",
+                    help="run the trace-correcting first run even when bench_run1.json holds its result")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (the method runs on one GPU with no sharding); got --gpus {args.gpus}",
               file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
+    import numpy as np  # noqa: F401
     import torch
 
     from fockgen import lattice_fock
@@ -341,9 +448,7 @@ def main():
         return
 
     cfg = dict(CONFIGS[args.config])
-    if args.precision:
-        cfg["precision"] = args.precision
-    L, tau, prec = cfg["L"], cfg["tau"], cfg["precision"]
+    L, tau, prec = cfg["L"], cfg["tau"], args.precision
     torch.cuda.set_device(0)
     t = time.perf_counter()
     Fh, info = lattice_fock(L, seed=0)
@@ -352,14 +457,22 @@ def main():
     no = info["n_occ"]
     lmin, lmax = sp2.gershgorin(F)
     opts = dict(accel=True, trunc_norm="frobinf", tau_fixed=tau, coarse_bs=4096)
+    run1 = None
     if args.bounds:
         hub, llb = (float(x) for x in args.bounds.split(","))
+        bounds_from = "given"
+    elif not args.run1 and run1_bounds(args.config, L, tau):
+        hub, llb = run1_bounds(args.config, L, tau)
+        bounds_from = "run 1 (trace-correcting FP64 run) recorded in bench_run1.json"
     else:
         t = time.perf_counter()
         r1 = sp2.density(F, no, lmin, lmax, **opts)
-        log(f"run 1 (trace-correcting): n={r1.n_iter} homo<={r1.homo_est!r} lumo>={r1.lumo_est!r} "
-            f"{time.perf_counter() - t:.2f} s")
+        run1 = {"L": L, "n": info["n"], "tau": tau, "homo_ub": r1.homo_est, "lumo_lb": r1.lumo_est,
+                "n_iter": r1.n_iter, "time_s": round(time.perf_counter() - t, 2)}
+        log(f"run 1 (trace-correcting): {json.dumps(run1)}")
         hub, llb = r1.homo_est, r1.lumo_est
+        bounds_from = "run 1 (trace-correcting FP64 run) in this job"
+        del r1
 
     if args.calibrate_copy_mib > 0:
         nb = args.calibrate_copy_mib << 20
@@ -371,7 +484,7 @@ def main():
         del src, dst
 
     if args.storage:
-        res = storage_bench(sp2, F, no, lmin, lmax, hub, llb, opts, args.precision or "fp64")
+        res = storage_bench(sp2, F, no, lmin, lmax, hub, llb, opts, "fp64" if prec == "bf16x3" else prec)
         print(json.dumps({"storage": res, "workload": f"lattice {L}^3 x 4, N={info['n']}, tau={tau}"}), flush=True)
         return
 
@@ -382,117 +495,96 @@ def main():
 
     correct = args.correct if args.correct is not None else (0 if prec == "fp64" else 1)
     switch_tol = args.switch_tol if args.switch_tol is not None else (0.0 if correct else 1e-3)
-    mopts = dict(precision=prec, correct=correct, switch_tol=switch_tol) if prec != "fp64" else dict(correct=correct)
+    mopts = dict(precision=prec, correct=correct)
+    if prec != "fp64":
+        mopts["switch_tol"] = switch_tol
     if args.corr_tol is not None:
         mopts["corr_tol"] = args.corr_tol
+    if correct and args.corr_mcweeny:
+        mopts["corr_mcweeny"] = 1
+        mopts["corr_purify"] = 1
+    if args.corr_purify is not None:
+        mopts["corr_purify"] = args.corr_purify
+    if args.corr_deriv_tol is not None:
+        mopts["corr_deriv_tol"] = args.corr_deriv_tol
     if args.n_max_cap is not None:
         mopts["n_max_cap"] = args.n_max_cap
 
-    def step():
-        return sp2.density(F, no, lmin, lmax, hub, llb, **mopts, **opts)
-
-    for _ in range(args.warmup):
-        r = step()
-        log(f"warmup: n={r.n_iter} {r.time_s:.3f} s  square kernels {r.square_time_s:.3f} s")
-    times, flops, ksq, res = [], [], [], None
-    torch.cuda.synchronize()
-    t_all = time.perf_counter()
-    for k in range(args.steps):
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        res = step()
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        times.append(dt)
-        flops.append(res.alg_flops - res.correction["corr_flops"])  # the expansion's own block products
-        ksq.append(res.square_time_s)
-        log(f"step {k}: n={res.n_iter} {dt:.3f} s  {flops[-1] / dt / 1e12:.2f} TFLOP/s  "
-            f"square kernels {res.square_time_s:.3f} s")
-        if k == 0:
-            it = res.iters
-            for i in range(res.n_iter + 1):
-                ks = it["square_time_s"][i]
-                log(f"   iter {i:2d} p={it['p'][i]:2d} nnzb={it['nnzb'][i]:7d} e={it['e'][i]:.3e} "
-                    f"flops={it['iter_flops'][i] / 1e12:8.3f} TF  square {ks * 1e3:8.2f} ms  "
-                    f"{it['iter_flops'][i] / max(ks, 1e-12) / 1e12:6.2f} TF/s  wall {it['iter_time_s'][i] * 1e3:8.2f} ms")
-    total = time.perf_counter() - t_all
-    ms = 1e3 * total / args.steps
-    value = sum(flops) / sum(times) / 1e12
-    # roofline of the dominant kernel: the expansion's squares in the run's
-    # bulk precision (code 0 FP64, 1 FP32, 2 BF16x3), flops / HIP-event time
+    # ---- the timed path, step by step
+    recs, res, t_timed = stepped_run(sp2, F, no, lmin, lmax, hub, llb, {**mopts, **opts}, args.warmup, args.steps)
+    first = [r for r in recs if r["solve"] == 0]
+    time_to_d = sum(r["wall"] for r in first)
+    exp_flops = sum(r["flops"] for r in first if r["kind"] == "iteration")
+    timed = [r for r in recs if r["phase"] == "timed"]
+    # roofline of the dominant kernel over the timed steps: the MFMA block-product
+    # kernels of the run's bulk arithmetic (HIP events on the library's stream)
     code = {"fp64": 0, "fp32": 1, "bf16x3": 2}[prec]
-    sel = res.iters["precision"] == code
-    achieved = float(res.iters["iter_flops"][sel].sum() / res.iters["square_time_s"][sel].sum() / 1e12)
-    mixed = {}
-    if prec == "fp64" and args.compare != "none":
-        t_ref = sum(times) / len(times)
-        for cor in (1, 0):
-            mo = dict(precision=args.compare, correct=cor, switch_tol=0.0 if cor else 1e-3)
-            if cor and args.corr_tol is not None:
-                mo["corr_tol"] = args.corr_tol
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            rm = sp2.density(F, no, lmin, lmax, hub, llb, **mo, **opts)
-            torch.cuda.synchronize()
-            dtm = time.perf_counter() - t0
-            err = bsr_diff_frobenius(rm.D, res.D)
-            key = args.compare + ("+correction" if cor else "+fp64_tail")
-            mixed[key] = {"time_to_D_s": round(dtm, 4), "speedup_vs_fp64": round(t_ref / dtm, 4),
-                          "err_vs_fp64_D": err, "n_iter": rm.n_iter, "switch_iter": rm.switch_iter,
-                          "correction": rm.correction}
-            log(f"mixed {key}: {dtm:.3f} s, speedup {t_ref / dtm:.2f}x, ||D - D_fp64||_F = {err:.3e}, "
-                f"correction {rm.correction}")
-            del rm
-        mixed = {"mixed": mixed}
-    if prec != "fp64" and args.no_reference:
-        mixed = {"switch_iter": res.switch_iter, "correction": res.correction}
-    elif prec != "fp64":
-        ref = sp2.density(F, no, lmin, lmax, hub, llb, precision="fp64", **opts)
-        err = bsr_diff_frobenius(res.D, ref.D)
-        mixed = {"err_vs_fp64_D": err, "fp64_time_to_D_s": ref.time_s, "speedup_vs_fp64": ref.time_s / (sum(times) / len(times)),
-                 "switch_iter": res.switch_iter, "switch_tol": switch_tol, "fp64_n_iter": ref.n_iter,
-                 "correction": res.correction}
-        log(f"mixed {prec}: ||D - D_fp64||_F = {err:.3e}, FP64 run {ref.time_s:.3f} s, speedup "
-            f"{mixed['speedup_vs_fp64']:.2f}x, switch at {res.switch_iter}, correction {res.correction}")
-    # tr D from the diagonal blocks (the first block of each block row when present), on the device
+    k_fl = sum(r["kernel_flops"][code] for r in timed)
+    k_s = sum(r["kernel_s"][code] for r in timed)
+    achieved = k_fl / k_s / 1e12 if k_s > 0 else 0.0
     D = res.D
-    first = D.row_ptr[:-1]
-    has = first < D.row_ptr[1:]
-    rows = torch.arange(D.nbr, device=D.device)[has]
-    dpos = first[has]
-    dpos = dpos[D.col_idx[dpos].to(torch.int64) == rows]
-    trD = float(torch.diagonal(D.val[dpos], dim1=1, dim2=2).sum())
+    checks = {"status": res.status, "stop": res.stop_reason, "n_iter": res.n_iter,
+              "trace_err": abs(trace_of(D) - no), "e_n": float(res.iters["e"][-1]),
+              "homo_est": None if math.isnan(res.homo_est) else res.homo_est,
+              "lumo_est": None if math.isnan(res.lumo_est) else res.lumo_est,
+              "steps_per_solve": len(first), "expansion_s": round(sum(r["wall"] for r in first
+                                                                     if r["kind"] == "iteration"), 3),
+              "correction": res.correction}
+    log(f"solve 0: {len(first)} steps, time to D {time_to_d:.3f} s, expansion {checks['expansion_s']:.3f} s, "
+        f"status {res.status} ({res.stop_reason}), n={res.n_iter}, e_n={checks['e_n']:.3e}, "
+        f"trace error {checks['trace_err']:.3e}")
+    del recs
+    if prec != "fp64" and not args.no_reference:
+        ctx = sp2.context(0)
+        ctx.trim()
+        torch.cuda.empty_cache()
+        t = time.perf_counter()
+        ref = sp2.density(F, no, lmin, lmax, hub, llb, precision="fp64", **opts)
+        torch.cuda.synchronize()
+        t_ref = time.perf_counter() - t
+        err = bsr_diff_frobenius(D, ref.D)
+        checks.update({"err_vs_fp64_D": err, "fp64_time_to_D_s": round(t_ref, 3),
+                       "speedup_vs_fp64": round(t_ref / time_to_d, 4), "fp64_status": ref.status,
+                       "fp64_stop": ref.stop_reason, "fp64_n_iter": ref.n_iter,
+                       "fp64_trace_err": abs(trace_of(ref.D) - no)})
+        log(f"FP64 reference: {t_ref:.3f} s, status {ref.status} ({ref.stop_reason}), n={ref.n_iter}; "
+            f"||D - D_fp64||_F = {err:.3e}, speedup {t_ref / time_to_d:.3f}x")
+        del ref
+    dtype = {"fp64": "f64", "fp32": "f32+f64", "bf16x3": "bf16x3+f64"}[prec]
     line = {
         "metric": "time-to-D (s), block-sparse TFLOP/s; mixed vs FP64 at ||D-D_ref||_F<=1e-5",
-        "value": round(value, 4),
+        "value": round(exp_flops / time_to_d / 1e12, 4),
         "unit": "TFLOP/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms, 3),
-        "time_to_D_s": round(sum(times) / len(times), 4),
+        "ms_per_step": round(1e3 * t_timed / args.steps, 3),
+        "time_to_D_s": round(time_to_d, 3),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if prec == "fp64" else prec,
+        "dtype": dtype,
         "data": "synthetic",
         "config": {
             "workload": f"tight-binding Fock {L}x{L}x{L} lattice x 4 basis fns (N={info['n']}), "
-                        f"{'FP64 SP2ACC' if prec == 'fp64' else prec + ' mixed SP2ACC'}"
+                        f"{'FP64 SP2ACC' if prec == 'fp64' else prec.upper() + ' SP2ACC'}"
                         f"{' + FP64 subspace correction' if correct else ''}, 64x64 blocks, "
-                        f"tau={tau} Frob-Inf(4096), Gershgorin bounds, homo/lumo from a trace-correcting run",
-            "n": info["n"], "n_occ": no, "tau": tau, "precision": prec,
-            "n_iter": res.n_iter, "stop": res.stop_reason, "max_nnzb": res.max_nnzb,
-            "alg_tflop_per_step": round(res.alg_flops / 1e12, 3),
+                        f"tau={tau} Frob-Inf(4096), Gershgorin bounds, homo/lumo from the trace-correcting run 1",
+            "n": info["n"], "n_occ": no, "tau": tau, "precision": prec, "bounds": [hub, llb],
+            "bounds_from": bounds_from,
+            "step": "one iteration of Algorithm 2 or one product of the subspace correction; value = the "
+                    "expansion's block-sparse flops / time to D of one solve (sum of its steps)",
+            "alg_tflop_expansion": round(exp_flops / 1e12, 3),
             "device_peak_gb": round(res.correction["device_peak_bytes"] / 1e9, 2),
         },
-        "checks": {"trace_err": abs(trD - no), "e_n": float(res.iters["e"][-1]),
-                   "homo_est": None if math.isnan(res.homo_est) else res.homo_est,
-                   "lumo_est": None if math.isnan(res.lumo_est) else res.lumo_est, **mixed},
+        "checks": checks,
         "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK[prec], "unit": "TFLOP/s",
                      "frac": round(achieved / PEAK[prec], 4), "traffic": traffic_per_launch(prec, L),
-                     "kernel": f"{KERNELS[prec][0]} (MFMA block-sparse symmetric square + fused epilogue)"},
+                     "kernel": f"{KERNELS[prec][0]} ({prec.upper()} MFMA block products, timed steps)"},
     }
+    if run1:
+        line["config"]["run1"] = run1
+    del D, res
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)...")
         line["cpu_baseline"] = cpu_baseline()

@@ -61,7 +61,9 @@ extern "C" {
 #define SP2_ERR_NONFINITE (-3)   /* F (or another input) holds NaN / Inf */
 #define SP2_ERR_OOM (-4)         /* device allocation failed */
 #define SP2_ERR_HIP (-5)         /* HIP runtime error */
-#define SP2_WARN_NOT_CONVERGED 1 /* n_max reached before the stopping criterion fired */
+#define SP2_WARN_NOT_CONVERGED 1 /* n_max reached before the stopping criterion fired (not raised when a
+                                    mixed run's FP64 tail reaches n_max before the criterion could be
+                                    evaluated: its two e values must come from FP64 squares) */
 #define SP2_WARN_TRACE 2         /* |tr D - n_occ| > 1/2: bounds wrong or gap closed */
 
 #define SP2_BLOCK 64
@@ -121,9 +123,19 @@ typedef struct {
   double corr_tol;      /* Frobenius budget for dropping small blocks of every intermediate of the
                            correction (0 = default 1e-9) */
   int64_t corr_mem;     /* device bytes for the copies of X~_i kept for the correction; the iterates
-                           beyond that are recomputed (0 = min(15% of the device, 25% of free memory)) */
+                           beyond that go to pinned host memory (corr_host_mem) or are recomputed
+                           (0 = min(25% of the device, 35% of free memory)) */
   int32_t adjoint_precision; /* arithmetic of sp2_vjp / sp2_jvp steps at the iterations the forward ran in
                            low precision: -1 = the forward's (default), else SP2_PREC_* */
+  double corr_deriv_tol;   /* the correction's derivative steps stop at the first X~_k with e_k below this
+                              (0 = default 1e-2) */
+  int32_t corr_mcweeny;    /* 1: each purification is one McWeeny step P' = 3P^2 - 2P^3 formed as
+                              S - (P R + R P) with S = P^2 an FP64 square and R = S - P, the small product
+                              P R + R P in the run's low arithmetic (corr_purify is then the number of such
+                              steps); 0: corr_purify FP64 squares X^2, 2X - X^2, ... */
+  int64_t corr_host_mem;   /* pinned host bytes for the copies of X~_i beyond corr_mem (written and read
+                              back on a second stream, overlapped with the squares); 0 = 75% of the
+                              available host memory, < 0 = none (those iterates are recomputed) */
 } sp2_options;
 
 /* Per-run statistics.  Arrays are HOST arrays owned by the caller, each of
@@ -164,6 +176,8 @@ typedef struct {
   double corr_e_last;      /* ||P - P^2||_F of the input P of the last purification square */
   int64_t corr_max_nnzb;   /* largest pattern among the correction's intermediates */
   int64_t seq_bytes;       /* device bytes of the stored X~_i sequence the correction replays */
+  int64_t seq_host_bytes;  /* pinned host bytes of the part of that sequence kept in host memory */
+  int32_t corr_recomputed; /* iterates the correction recomputed (not stored) */
   int64_t device_peak_bytes; /* largest device memory the library held at once during the call */
 } sp2_stats;
 
@@ -223,10 +237,12 @@ int sp2_gershgorin(sp2_ctx *ctx, const sp2_bsr *F, double *lmin, double *lmax);
  * switch_tol = 0 the expansion runs in the low precision to its stopping
  * criterion (evaluated on the low-precision e_i) and the purification replaces
  * the FP64 tail.  Copies of X~_0, X~_1, ... are kept on the device within
- * corr_mem bytes (stats->seq_bytes); later iterates are recomputed from their
- * recorded masks and polynomials, bit for bit.  Derivative steps from the
- * first iterate with e_i < 1e-3 on are skipped: near a projector they only
- * keep the occupied-virtual part, which the purification leaves in place. */
+ * corr_mem bytes (stats->seq_bytes), then in pinned host memory within
+ * corr_host_mem bytes (stats->seq_host_bytes); iterates beyond both are
+ * recomputed from their recorded masks and polynomials, bit for bit.
+ * Derivative steps from the first iterate with e_i < corr_deriv_tol on are
+ * skipped: near a projector they only keep the occupied-virtual part, which
+ * the purification leaves in place. */
 
 /* Density matrix by SP2 / SP2ACC (Steps 1-3, Algorithms 1-2).
  *   F         symmetric input in upper BSR (device)

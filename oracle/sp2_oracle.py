@@ -745,7 +745,7 @@ def _drop_small_blocks(X, beta, bs):
 
 
 def subspace_correction(F, D, X_seq, p, alpha, lmin, lmax, *, rounds=1, purify=2, beta=0.0, tau_purify=0.0,
-                        trunc_norm=TRUNC_FROBINF, coarse_bs=4096, bs=BS):
+                        trunc_norm=TRUNC_FROBINF, coarse_bs=4096, bs=BS, purify_form="sp2"):
     """First-order correction of the occupied subspace of a near-projector D,
     for expansions whose squares ran in low precision: the paper notes (section
     "Error control") that an error in the occupied subspace made by one
@@ -764,9 +764,12 @@ def subspace_correction(F, D, X_seq, p, alpha, lmin, lmax, *, rounds=1, purify=2
         p = 0: dX_i = 2 a dX~ - a^2 (X~_{i-1} dX~ + dX~ X~_{i-1}),
     without the run's masks.  C = [D, F], Delta and every dX_i lose their
     smallest blocks within the Frobenius budget ``beta`` (0 = keep all).  Then
-    ``purify`` FP64 steps X^2, 2X - X^2, ... (each truncated with tau_purify in
-    ``trunc_norm``) restore idempotency.  Returns (D, info) with the norms of
-    Delta and of the correction of the last round."""
+    ``purify`` FP64 steps restore idempotency, each truncated with tau_purify
+    in ``trunc_norm``: X^2, 2X - X^2, ... (``purify_form="sp2"``) or McWeeny's
+    3X^2 - 2X^3 (``"mcweeny"``), which maps every eigenvalue x to
+    3x^2 - 2x^3 and so moves both clusters toward 0 and 1 quadratically in one
+    step.  Returns (D, info) with the norms of Delta and of the correction of
+    the last round."""
     F = np.asarray(F, dtype=np.float64)
     D = np.asarray(D, dtype=np.float64)
     w = lmax - lmin
@@ -790,8 +793,17 @@ def subspace_correction(F, D, X_seq, p, alpha, lmin, lmax, *, rounds=1, purify=2
         M = structural_mask(P, bs)
         M[np.arange(M.shape[0]), np.arange(M.shape[0])] = True
         for k in range(purify):
-            X = P @ P if k % 2 == 0 else 2.0 * P - P @ P
-            P, M, _ = truncate(X, pattern_square(M), tau_purify, trunc_norm, bs, coarse_bs)
+            if purify_form == "mcweeny":
+                S = P @ P
+                X = 3.0 * S - 2.0 * (P @ S)
+                M2 = pattern_square(M)
+                MX = (M.astype(np.int64) @ M2.astype(np.int64)) > 0
+            elif purify_form == "sp2":
+                X = P @ P if k % 2 == 0 else 2.0 * P - P @ P
+                MX = pattern_square(M)
+            else:
+                raise OracleError(f"unknown purification {purify_form!r}")
+            P, M, _ = truncate(X, MX, tau_purify, trunc_norm, bs, coarse_bs)
         D = P
     return D, info
 

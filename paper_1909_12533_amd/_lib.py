@@ -61,6 +61,9 @@ class sp2_options(C.Structure):
         ("corr_tol", C.c_double),
         ("corr_mem", C.c_int64),
         ("adjoint_precision", C.c_int32),
+        ("corr_deriv_tol", C.c_double),
+        ("corr_mcweeny", C.c_int32),
+        ("corr_host_mem", C.c_int64),
     ]
 
 
@@ -105,6 +108,8 @@ class sp2_stats(C.Structure):
         ("corr_e_last", C.c_double),
         ("corr_max_nnzb", C.c_int64),
         ("seq_bytes", C.c_int64),
+        ("seq_host_bytes", C.c_int64),
+        ("corr_recomputed", C.c_int32),
         ("device_peak_bytes", C.c_int64),
     ]
 

@@ -33,6 +33,8 @@ namespace sp2 {
 constexpr int B = 64;          // block size
 constexpr int BB = B * B;      // elements per block
 constexpr int MAX_NBR = 32768; // dense block maps are nbr^2 int32
+constexpr size_t BIG_BUFFER = (size_t)64 << 20;  // device buffers above this size are rounded coarsely
+constexpr size_t FREE_RESERVE = (size_t)8 << 30;  // device memory kept free of cached library buffers
 
 struct Exc {
   int code;
@@ -84,8 +86,16 @@ struct Ctx {
   // launched so far, by arithmetic (Mode); read by the stepped solver
   double kern_s[3] = {0.0, 0.0, 0.0};
   double kern_flops[3] = {0.0, 0.0, 0.0};
+  // calls into the device allocator and the host time they took
+  int64_t n_raw_alloc = 0, n_raw_free = 0;
+  double raw_alloc_s = 0.0, raw_free_s = 0.0;
   double *h_pinned = nullptr;  // pinned host staging for small device->host reads
   size_t h_pinned_bytes = 0;
+
+  // second stream (default priority) for host <-> device copies that overlap
+  // the kernels of `stream`; created on first use
+  hipStream_t copy_stream = nullptr;
+  hipStream_t copies();
 
   Buf alloc(size_t bytes);
   void release(void *p, size_t bytes);
@@ -176,6 +186,9 @@ void launch_minmax(Ctx &c, const double *lo, const double *hi, int n, double *ou
 void launch_gather(Ctx &c, const void *src, int src_prec, const int32_t *slot, int64_t nblocks, void *dst,
                    int dst_prec);
 void launch_reduce_parts(Ctx &c, const double *parts, int64_t nrows, int ncols, double *out);
+// the same reduction with a caller-supplied staging buffer of reduce_stage_doubles(ncols) doubles
+void launch_reduce_parts(Ctx &c, const double *parts, int64_t nrows, int ncols, double *out, double *stage);
+constexpr int64_t reduce_stage_doubles(int ncols) { return (int64_t)256 * ncols; }
 void launch_block_norms(Ctx &c, const void *pool, int prec, const int32_t *slot, int64_t nblocks, double *nrm2);
 // pair: nc (nc + 1) / 2 doubles (packed upper coarse squared norms); rowsum: nc
 void launch_coarse_rowsums(Ctx &c, const int64_t *row_ptr, const int32_t *col_idx, const double *nrm2, int nbr,

@@ -426,8 +426,24 @@ __global__ __launch_bounds__(512, 2) void k_square_tile4_bf16x3(TileArgs a) {
   // f32 16 x 16 accumulator layout: element v of lane group g is row 4 g + v;
   // nk counted both k halves of every K
   const auto rowf = [](int gg, int qq) { return 4 * gg + qq; };
+  // Block 1's accumulators wait in the (now idle) LDS stages, 16 KB per wave,
+  // while block 0's epilogue runs, so the two never hold registers at once
+  // (8 waves leave 256 registers per lane; both blocks plus the FP64
+  // epilogue do not fit).
+  __syncthreads();  // every wave is done with S0 / S1
+  f4 *park = reinterpret_cast<f4 *>(wave < 4 ? &S0[0][0][0] : &S1[0][0][0]) + (wave & 3) * 1024;
+#pragma unroll
+  for (int m = 0; m < 4; ++m)
+#pragma unroll
+    for (int n = 0; n < 4; ++n) park[(m * 4 + n) * 64 + lane] = acc1[m][n];
   if (pos0 >= 0) square_epilogue<float, TO>(acc0, a, I, Jb0, pos0, nk0 / 2, rowf);
-  if (pos1 >= 0) square_epilogue<float, TO>(acc1, a, I, Jb1, pos1, nk1 / 2, rowf);
+  asm volatile("" ::: "memory");  // keep the reload below block 0's epilogue
+  f4 acc2[4][4];
+#pragma unroll
+  for (int m = 0; m < 4; ++m)
+#pragma unroll
+    for (int n = 0; n < 4; ++n) acc2[m][n] = park[(m * 4 + n) * 64 + lane];
+  if (pos1 >= 0) square_epilogue<float, TO>(acc2, a, I, Jb1, pos1, nk1 / 2, rowf);
 }
 
 }  // namespace

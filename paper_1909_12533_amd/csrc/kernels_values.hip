@@ -11,6 +11,7 @@ namespace {
 
 constexpr int TPB = 256;
 constexpr int RED_BLOCKS = 256;  // fixed, so reductions are reproducible on any device
+static_assert(reduce_stage_doubles(1) == RED_BLOCKS, "staging size of launch_reduce_parts");
 
 __global__ void k_check_finite(const double *v, int64_t n, int32_t *flag) {
   bool bad = false;
@@ -344,12 +345,16 @@ void launch_sym_diag(Ctx &c, void *pool, int prec, const int64_t *row_ptr, const
   SP2_LAUNCH_CHECK();
 }
 
+void launch_reduce_parts(Ctx &c, const double *parts, int64_t nrows, int ncols, double *out, double *stage) {
+  k_reduce_stage1<<<RED_BLOCKS, TPB, 0, c.stream>>>(parts, nrows, ncols, stage);
+  SP2_LAUNCH_CHECK();
+  k_reduce_stage2<<<1, TPB, 0, c.stream>>>(stage, RED_BLOCKS, ncols, out);
+  SP2_LAUNCH_CHECK();
+}
+
 void launch_reduce_parts(Ctx &c, const double *parts, int64_t nrows, int ncols, double *out) {
   Buf stage = c.alloc(sizeof(double) * RED_BLOCKS * ncols);
-  k_reduce_stage1<<<RED_BLOCKS, TPB, 0, c.stream>>>(parts, nrows, ncols, stage.as<double>());
-  SP2_LAUNCH_CHECK();
-  k_reduce_stage2<<<1, TPB, 0, c.stream>>>(stage.as<double>(), RED_BLOCKS, ncols, out);
-  SP2_LAUNCH_CHECK();
+  launch_reduce_parts(c, parts, nrows, ncols, out, stage.as<double>());
 }
 
 void launch_block_norms(Ctx &c, const void *pool, int prec, const int32_t *slot, int64_t nblocks, double *nrm2) {

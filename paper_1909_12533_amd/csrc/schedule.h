@@ -119,21 +119,41 @@ inline void poly_coeffs(int p, double alpha, double &a, double &b, double &c) {
   }
 }
 
+// Rounding noise of e_i = ||X~ - X~^2||_F when the square S = X~^2 is formed
+// in low precision: the Frobenius norm of S's rounding error, which behaves
+// as kappa sqrt(tr X~) (rounding errors of the ~tr X~ significant rows add up
+// at random).  kappa is twice the largest ratio |e_low - e_FP64| / sqrt(tr X~)
+// measured at the FP32 / BF16x3 noise floor of the lattice expansions
+// (N = 2,048 .. 108,000: FP32 0.7-2.3e-6, BF16x3 4.2-8.1e-6); FP64 squares
+// have none at this scale (0).
+inline double e_noise(int low_kind, double trX) {
+  const double kappa = low_kind == 1 ? 4e-6 : (low_kind == 2 ? 1.6e-5 : 0.0);
+  return kappa * std::sqrt(std::fmax(trX, 1.0));
+}
+
 // Step 3 estimates.  e[i], tr[i] of X~_i; p, alpha of the run; sched holds
 // the forward bounds in bounds mode.  Returns {homo_ub, lumo_lb} (NaN if none).
+// noise[i] (optional): rounding noise of a low-precision e_i (0 for FP64).
 inline void homo_lumo(const Sched &s, const std::vector<double> &e, const std::vector<double> &tr,
                       const std::vector<int> &p, const std::vector<double> &alpha, int n, double lmin, double lmax,
-                      int64_t N, int64_t n_occ, double &homo, double &lumo, const std::vector<double> *unit = nullptr) {
-  // e_i below 1e3 u sqrt(N) is rounding noise rather than an eigenvalue's
-  // distance from {0, 1}; u = 2^-52, or per iteration the unit roundoff of
-  // the arithmetic that produced e_i (unit[i])
+                      int64_t N, int64_t n_occ, double &homo, double &lumo, const std::vector<double> *noise = nullptr) {
+  // An FP64 e_i below 1e3 * 2^-52 * sqrt(N) is rounding noise rather than an
+  // eigenvalue's distance from {0, 1}.  A low-precision e_i is used when it is
+  // at least ten times its noise nu_i, and as e_i + nu_i (an upper estimate of
+  // the e of the exactly squared iterate).
   const double w = lmax - lmin;
   double bh = std::numeric_limits<double>::infinity();
   double bl = -std::numeric_limits<double>::infinity();
   for (int i = 0; i <= n; ++i) {
-    const double ei = e[i];
-    const double e_floor = 1e3 * (unit ? (*unit)[i] : DELTA_N) * std::sqrt((double)N);
-    if (!(ei >= e_floor && ei < 0.25)) continue;
+    const double nu = noise ? (*noise)[i] : 0.0;
+    double ei = e[i];
+    if (nu > 0.0) {
+      if (!(ei >= 10.0 * nu)) continue;
+      ei += nu;
+    } else if (!(ei >= 1e3 * DELTA_N * std::sqrt((double)N))) {
+      continue;
+    }
+    if (!(ei < 0.25)) continue;
     const double u = 2.0 * ei / (1.0 + std::sqrt(1.0 - 4.0 * ei));
     bool ok;
     if (s.bounds)

@@ -11,6 +11,8 @@
 //   Step 3   homo/lumo estimates from e_i and t_i (host).
 // The only device -> host traffic per iteration is a handful of scalars and
 // the sizes needed to allocate the next pattern.
+#include <unistd.h>
+
 #include <chrono>
 #include <map>
 #include <cstdlib>
@@ -602,13 +604,36 @@ void restrict_to(Ctx &c, DMat &X, const Pattern &mask) {
   X.pat = std::move(np);
 }
 
-// low-precision square cannot resolve e below ~ unit roundoff * ||X||_F
-double low_floor(int mode, double trX) {
-  const double u = (mode == M_BF16X3) ? 1.0 / 65536.0 : 1.0 / 16777216.0;
-  return 8.0 * u * std::sqrt(std::fmax(trX, 1.0));
-}
+// a low-precision square resolves e down to about ten times its rounding noise
+double low_floor(int mode, double trX) { return 10.0 * e_noise(mode, trX); }
 
 }  // namespace
+
+// Values of an iterate kept in pinned host memory.  The device -> host copy
+// runs on the context's copy stream while the main stream goes on with the
+// square of the same iterate; the device pool is held until the copy has
+// completed (wait()).
+struct HostCopy {
+  Pattern pat;                 // device pattern of the iterate (slots included)
+  int prec = P32;
+  int64_t nslots = 0;
+  void *host = nullptr;
+  size_t bytes = 0;
+  hipEvent_t ready = nullptr;  // the values are complete on the main stream
+  hipEvent_t done = nullptr;   // the device -> host copy has completed
+  std::shared_ptr<Pool> src;   // the device pool until the copy completed
+  void wait() {
+    if (src && done) (void)hipEventSynchronize(done);
+    src.reset();
+  }
+  ~HostCopy() {
+    if (done) (void)hipEventSynchronize(done);
+    src.reset();
+    if (host) (void)hipHostFree(host);
+    if (ready) (void)hipEventDestroy(ready);
+    if (done) (void)hipEventDestroy(done);
+  }
+};
 
 struct TapeIter {
   Pattern mask;                  // block pattern of X~_i
@@ -617,6 +642,7 @@ struct TapeIter {
   int mode = M_F64;              // arithmetic of the square of X~_i
   int prec = P64;                // storage precision of X~_i
   std::shared_ptr<DMat> ckpt;    // compact copy of X~_i, or empty
+  std::shared_ptr<HostCopy> hcopy;  // copy of X~_i in pinned host memory, or empty
 };
 
 struct Tape {
@@ -666,6 +692,11 @@ void add_checkpoint(Ctx &c, Tape &t, int i, const DMat &X) {
 
 constexpr double FL_BLOCK = 2.0 * B * B * B;  // flops of one 64 x 64 x 64 block product
 
+int64_t available_host_bytes() {
+  const long pages = sysconf(_SC_AVPHYS_PAGES), psz = sysconf(_SC_PAGESIZE);
+  return (pages > 0 && psz > 0) ? (int64_t)pages * (int64_t)psz : 0;
+}
+
 double seconds_since(std::chrono::steady_clock::time_point t0) {
   return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
 }
@@ -697,20 +728,28 @@ struct Solver {
   std::vector<int> p{-1}, precv;
   std::vector<int64_t> nnzbv;
   int switch_iter = -1, n = -1, stop_reason = 0, status = SP2_OK;
+  bool criterion_seen = false;  // the stopping test was evaluated at an admissible iteration
   double alg_flops = 0.0;
   int64_t max_nnzb = 0, seq_bytes = 0;
   // ---- iterates recorded for the correction (masks, polynomials, a prefix of copies)
   Tape ct;
   int64_t seq_budget = 0;
   bool seq_full = false;
+  int64_t host_budget = 0, host_bytes = 0;
+  bool host_full = false;
+  int n_recomputed = 0;
+  std::vector<std::shared_ptr<HostCopy>> pending;  // host copies still holding their device pools
+  int pf_k = -1;                                   // iterate being prefetched from host memory
+  DMat pf_X;
+  hipEvent_t pf_ready = nullptr, pf_done = nullptr;
   // ---- correction state
   enum Phase { EXPAND, CORRECT, FINISHED, FAILED };
   enum CStage { C_COMM, C_DELTA, C_DERIV, C_PURIFY };
   Phase phase = EXPAND;
   CStage cstage = C_COMM;
-  int cround = 0, ck = 0, n_deriv = 0;
-  double beta = 1e-9;
-  DMat C, dX, Xi;
+  int cround = 0, ck = 0, csub = 0, n_deriv = 0;
+  double beta = 1e-9, deriv_tol = 1e-3;
+  DMat C, dX, Xi, Rm;
   CorrStats cs;
   // ---- accounting
   double busy_s = 0.0;     // time spent inside begin / step / finish
@@ -718,6 +757,7 @@ struct Solver {
   sp2_step_info info{};    // facts of the last step
 
   explicit Solver(Ctx &ctx) : c(ctx) {}
+  ~Solver();
   void begin(const sp2_bsr *Fin, int64_t n_occ_, double lmin_, double lmax_, const double *hub, const double *llb,
              const sp2_options &opt);
   bool step();
@@ -725,6 +765,9 @@ struct Solver {
 
  private:
   void iterate();
+  void record_iterate(int mode);
+  std::shared_ptr<HostCopy> host_store(const DMat &M);
+  DMat host_load(const HostCopy &h);
   void correct_step();
   void note(const DMat &M) { cs.max_nnzb = std::max(cs.max_nnzb, M.pat.nnzb); }
   // blocks of a correction intermediate dropped within the Frobenius budget beta
@@ -813,7 +856,12 @@ void Solver::begin(const sp2_bsr *Fin, int64_t n_occ_, double lmin_, double lmax
   if (corr) {
     size_t fr = 0, tot = 0;
     SP2_HIP(hipMemGetInfo(&fr, &tot));
-    seq_budget = o.corr_mem > 0 ? o.corr_mem : (int64_t)std::min(0.15 * (double)tot, 0.25 * (double)fr);
+    seq_budget = o.corr_mem > 0 ? o.corr_mem : (int64_t)std::min(0.25 * (double)tot, 0.35 * (double)fr);
+    host_budget = o.corr_host_mem > 0 ? o.corr_host_mem
+                  : (o.corr_host_mem < 0 ? 0 : (int64_t)(0.75 * (double)available_host_bytes()));
+    deriv_tol = o.corr_deriv_tol > 0.0 ? o.corr_deriv_tol : 1e-2;
+    SP2_HIP(hipEventCreateWithFlags(&pf_ready, hipEventDisableTiming));
+    SP2_HIP(hipEventCreateWithFlags(&pf_done, hipEventDisableTiming));
     ct.ctx = &c;
     ct.n = N;
     ct.lmax = lmax;
@@ -821,6 +869,100 @@ void Solver::begin(const sp2_bsr *Fin, int64_t n_occ_, double lmin_, double lmax
   }
   c.sync();
   busy_s += seconds_since(t0);
+}
+
+Solver::~Solver() {
+  // no copy on the second stream may outlive the buffers it reads or writes
+  if (pf_done) (void)hipStreamWaitEvent(c.stream, pf_done, 0);
+  if (c.copy_stream) (void)hipStreamSynchronize(c.copy_stream);
+  pf_X = DMat();
+  pending.clear();
+  ct.it.clear();
+  if (pf_ready) (void)hipEventDestroy(pf_ready);
+  if (pf_done) (void)hipEventDestroy(pf_done);
+}
+
+// X~_i for the correction: its mask and polynomial, and a copy on the device
+// (while corr_mem lasts), in pinned host memory (while corr_host_mem lasts)
+// or none (recomputed from the previous iterate when needed)
+void Solver::record_iterate(int mode) {
+  // copies started in earlier iterations ran under their own squares: they
+  // have completed, and their device pools can go
+  for (auto &h : pending) h->wait();
+  pending.clear();
+  ct.it.emplace_back();
+  TapeIter &ti = ct.it.back();
+  ti.mask = clone_pattern(c, X.pat);
+  ti.mask.slot.reset();
+  ti.mode = mode;
+  ti.prec = X.pool->prec;
+  if (i >= 1) {
+    ti.p = p[i];
+    ti.alpha = alph[i];
+    poly_coeffs(p[i], alph[i], ti.ca, ti.cb, ti.cc);
+  }
+  // the derivative steps stop before the first X~_k (k >= 1) with e_k below
+  // corr_deriv_tol: once one has been seen, later iterates are never used
+  for (int k = 1; k < i; ++k)
+    if (e[k] < deriv_tol) return;
+  const int64_t esz = X.pool->prec == P64 ? 8 : 4;
+  const int64_t bytes = X.pat.nnzb * (int64_t)BB * esz;
+  if (i == 0 || (!seq_full && seq_bytes + bytes <= seq_budget)) {
+    add_checkpoint(c, ct, i, X);
+    seq_bytes += bytes;
+    return;
+  }
+  seq_full = true;
+  const int64_t hb = X.pool->nslots * (int64_t)BB * esz;
+  if (!host_full && host_bytes + hb <= host_budget) {
+    if (auto h = host_store(X)) {
+      ti.hcopy = h;
+      host_bytes += hb;
+      pending.push_back(h);
+      return;
+    }
+  }
+  host_full = true;
+}
+
+// start copying the value pool of M to pinned host memory on the copy stream
+// (after the work already queued on the main stream); null when the host
+// allocation fails
+std::shared_ptr<HostCopy> Solver::host_store(const DMat &M) {
+  auto h = std::make_shared<HostCopy>();
+  h->prec = M.pool->prec;
+  h->nslots = M.pool->nslots;
+  h->bytes = (size_t)std::max<int64_t>(M.pool->nslots, 1) * BB * (h->prec == P64 ? 8 : 4);
+  if (hipHostMalloc(&h->host, h->bytes, hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    h->host = nullptr;
+    return nullptr;
+  }
+  h->pat = clone_pattern(c, M.pat);
+  hipStream_t cs = c.copies();
+  SP2_HIP(hipEventCreateWithFlags(&h->ready, hipEventDisableTiming));
+  SP2_HIP(hipEventCreateWithFlags(&h->done, hipEventDisableTiming));
+  SP2_HIP(hipEventRecord(h->ready, c.stream));
+  SP2_HIP(hipStreamWaitEvent(cs, h->ready, 0));
+  SP2_HIP(hipMemcpyAsync(h->host, M.pool->vals.p, h->bytes, hipMemcpyDeviceToHost, cs));
+  SP2_HIP(hipEventRecord(h->done, cs));
+  h->src = M.pool;
+  return h;
+}
+
+// device copy of a host-stored iterate; the host -> device copy runs on the
+// copy stream and pf_done marks its completion (the main stream must wait on
+// it before the values are used)
+DMat Solver::host_load(const HostCopy &h) {
+  DMat d;
+  d.pat = clone_pattern(c, h.pat);
+  d.pool = new_pool(c, h.prec, h.nslots);
+  hipStream_t cs = c.copies();
+  SP2_HIP(hipEventRecord(pf_ready, c.stream));  // earlier users of the new buffer are done
+  SP2_HIP(hipStreamWaitEvent(cs, pf_ready, 0));
+  SP2_HIP(hipMemcpyAsync(d.pool->vals.p, h.host, h.bytes, hipMemcpyHostToDevice, cs));
+  SP2_HIP(hipEventRecord(pf_done, cs));
+  return d;
 }
 
 // one iteration of Algorithm 2
@@ -842,6 +984,7 @@ void Solver::iterate() {
     const int64_t ckb = X.pat.nnzb * (int64_t)BB * (X.pool->prec == P64 ? 8 : 4);
     if (i % ck_every == 0 && (i == 0 || tape->bytes + ckb <= tape_budget)) add_checkpoint(c, *tape, i, X);
   }
+  if (corr) record_iterate(mode);
   nnzbv.push_back(X.pat.nnzb);
   max_nnzb = std::max(max_nnzb, X.pat.nnzb);
   precv.push_back(mode == M_F64 ? SP2_PREC_FP64 : o.precision);
@@ -863,12 +1006,17 @@ void Solver::iterate() {
   last_flops = fl;
 
   // ---- stopping test (Algorithm 2) -----------------------------------------
-  // the criterion compares e_i with e_{i-2}: both must come from FP64 squares
+  // the criterion compares e_i with e_{i-2}: both from FP64 squares, the
+  // older one of an iterate the FP64 tail has already squared once (the
+  // first FP64 iterates still carry the low-precision rounding, which two
+  // FP64 squares remove; stopping on it would end at the low-precision floor)
   bool stop = false;
   const bool fp64_window = mode == M_F64 && (switch_iter >= 0 && i >= switch_iter + 2);
   const bool low_window = low_to_end && mode != M_F64;
+  const bool admissible = i >= std::max(sch.n_min, 2) && p[i] != p[i - 1];
   if (i >= 1 && (fp64_window || low_window)) {
-    if (i >= std::max(sch.n_min, 2) && p[i] != p[i - 1] && e[i] > C_STOP * e[i - 2] * e[i - 2]) {
+    if (admissible) criterion_seen = true;
+    if (admissible && e[i] > C_STOP * e[i - 2] * e[i - 2]) {
       stop = true;
       stop_reason = SP2_STOP_CRITERION;
     } else if (o.idem_stop > 0.0 && e[i] <= o.idem_stop) {
@@ -879,10 +1027,14 @@ void Solver::iterate() {
   if (!stop && i == n_max) {
     stop = true;
     stop_reason = SP2_STOP_NMAX;
-    status = SP2_WARN_NOT_CONVERGED;
+    // a warning when the criterion could have fired and did not; an FP64
+    // tail that reaches n_max before its first admissible test ends where
+    // the schedule (valid bounds) places convergence
+    if (criterion_seen || switch_iter <= 0) status = SP2_WARN_NOT_CONVERGED;
   }
   if (stop) {
     n = i;
+    if (corr) ct.it.pop_back();  // the correction replays X~_0 .. X~_{n-1}
     c.sync();
     itime.push_back(seconds_since(t_it));
     phase = corr ? CORRECT : FINISHED;
@@ -905,26 +1057,6 @@ void Solver::iterate() {
   }
   p.push_back(pn);
   alph.push_back(an);
-  if (corr) {
-    ct.it.emplace_back();
-    TapeIter &ti = ct.it.back();
-    ti.mask = clone_pattern(c, X.pat);
-    ti.mask.slot.reset();
-    ti.mode = mode;
-    ti.prec = X.pool->prec;
-    if (i >= 1) {
-      ti.p = p[i];
-      ti.alpha = alph[i];
-      poly_coeffs(p[i], alph[i], ti.ca, ti.cb, ti.cc);
-    }
-    const int64_t bytes = X.pat.nnzb * (int64_t)BB * (X.pool->prec == P64 ? 8 : 4);
-    if (i == 0 || (!seq_full && seq_bytes + bytes <= seq_budget)) {
-      add_checkpoint(c, ct, i, X);
-      seq_bytes += bytes;
-    } else {
-      seq_full = true;
-    }
-  }
   DMat Xn = std::move(so.next);
   const int64_t nout = Xn.pat.nnzb;
   X = DMat{};  // X~_i is not needed any more: release it before X_{i+1} is compacted
@@ -972,10 +1104,12 @@ void Solver::correct_step() {
         // change the correction only at relative order e_i and are skipped.
         n_deriv = n;
         for (int k = 1; k < n; ++k)
-          if (e[k] < 1e-3) {
+          if (e[k] < deriv_tol) {
             n_deriv = k;
             break;
           }
+        for (auto &h : pending) h->wait();
+        pending.clear();
         // the symmetric part of D: a low-precision iterate's diagonal blocks
         // carry antisymmetric rounding noise, which the correction must not see
         X = compact_values(c, X, X.pool->prec);
@@ -1025,7 +1159,33 @@ void Solver::correct_step() {
     case C_DERIV: {
       // derivative of X_{k+1} = ca I + cb X~_k + cc X~_k^2 along dX~_k
       const int k = ck;
-      Xi = ct.it[k].ckpt ? checkpoint_copy(ct, k) : replay_step(c, ct, k, Xi);
+      TapeIter &tk = ct.it[k];
+      const char *src = "";
+      if (tk.ckpt) {
+        Xi = checkpoint_copy(ct, k);
+      } else if (pf_k == k) {
+        SP2_HIP(hipStreamWaitEvent(c.stream, pf_done, 0));
+        Xi = std::move(pf_X);
+        pf_k = -1;
+        src = " (host copy)";
+      } else if (tk.hcopy) {
+        Xi = host_load(*tk.hcopy);
+        SP2_HIP(hipStreamWaitEvent(c.stream, pf_done, 0));
+        src = " (host copy)";
+      } else {
+        Xi = replay_step(c, ct, k, Xi);
+        ++n_recomputed;
+        src = " (recomputed iterate)";
+      }
+      if (cround == o.correct - 1) {  // the last round needs X~_k only here
+        tk.ckpt.reset();
+        tk.hcopy.reset();
+      }
+      // the next host-stored iterate comes back under this step's product
+      if (k + 1 < n_deriv && !ct.it[k + 1].ckpt && ct.it[k + 1].hcopy) {
+        pf_X = host_load(*ct.it[k + 1].hcopy);
+        pf_k = k + 1;
+      }
       const int mi = Xi.pool->prec == P32 ? lowmode : M_F64;
       DMat G = as_prec(c, dX, Xi.pool->prec);
       Maps mX = build_maps(c, Xi.pat, true), mG = build_maps(c, G.pat, true);
@@ -1044,12 +1204,58 @@ void Solver::correct_step() {
       drop(dX, jo);
       if (verbose())
         std::fprintf(stderr, "[sp2] correction: derivative step %d/%d nnzb=%lld%s product %.1f ms\n", k + 1,
-                     n_deriv, (long long)dX.pat.nnzb, ct.it[k].ckpt ? "" : " (recomputed iterate)",
-                     1e3 * jo.kernel_s);
+                     n_deriv, (long long)dX.pat.nnzb, src, 1e3 * jo.kernel_s);
       ++ck;
       break;
     }
     case C_PURIFY: {
+      if (o.corr_mcweeny && csub == 0) {
+        // S = P^2 in FP64, written as R = S - P by the square's epilogue; R is
+        // small, so its low-precision copy loses nothing the target can see
+        Maps m = build_maps(c, X.pat, true);
+        SquareOut so = square_step(c, X, m, M_F64, P64, 0.0, -1.0, 1.0);
+        last_flops = so.sums[4] * FL_BLOCK;
+        cs.e_last = std::sqrt(std::fmax(so.sums[0], 0.0));
+        note(so.next);
+        Rm = compact_values(c, so.next, lp);
+        if (verbose())
+          std::fprintf(stderr, "[sp2] correction: McWeeny %d: R = P^2 - P, e=%.3e square %.1f ms\n", ck, cs.e_last,
+                       1e3 * so.kernel_s);
+        csub = 1;
+        break;
+      }
+      if (o.corr_mcweeny) {
+        // P' = 3 P^2 - 2 P^3 = P + R - (P R + R P), the product in the low arithmetic
+        SquareOut to;
+        {
+          DMat Pl = as_prec(c, X, lp);
+          Maps mP = build_maps(c, Pl.pat, true), mR = build_maps(c, Rm.pat, true);
+          PairOpt pt;
+          pt.mode = lowmode;
+          pt.oprec = lp;
+          to = pair_product(c, Pl, mP, Rm, mR, pt);
+        }
+        last_flops = to.sums[4] * FL_BLOCK;
+        note(to.next);
+        DMat PR = add_union(c, X, 1.0, Rm, 1.0);
+        Rm = DMat();
+        X = DMat();
+        X = add_union(c, PR, 1.0, to.next, -1.0);
+        PR = DMat();
+        to = SquareOut();
+        Buf nrm2 = norms_of(c, X);
+        truncate_matrix(c, X, nrm2.as<double>(), taus[n], o.trunc_norm, o.coarse_bs);
+        if (verbose()) std::fprintf(stderr, "[sp2] correction: McWeeny %d: P' = P + R - (P R + R P)\n", ck);
+        csub = 0;
+        ++ck;
+        if (ck == o.corr_purify) {
+          cs.rounds++;
+          cround++;
+          cstage = C_COMM;
+          if (cround == o.correct) phase = FINISHED;
+        }
+        break;
+      }
       double ca, cb, cc;
       poly_coeffs(ck % 2 == 0 ? 1 : 0, 1.0, ca, cb, cc);
       Maps m = build_maps(c, X.pat, true);
@@ -1140,10 +1346,10 @@ int Solver::finish(sp2_bsr **D_out, double *hest, double *lest, sp2_stats *st, s
   // ---- Step 3 and outputs ---------------------------------------------------------
   double h = NaN, l = NaN;
   {
-    std::vector<double> unit(n + 1);
+    std::vector<double> noise(n + 1);
     for (int k = 0; k <= n; ++k)
-      unit[k] = precv[k] == SP2_PREC_FP64 ? DELTA_N : (precv[k] == SP2_PREC_FP32 ? 1.0 / 16777216.0 : 1.0 / 65536.0);
-    homo_lumo(sch, e, trv, p, alph, n, lmin, lmax, N, n_occ, h, l, &unit);
+      noise[k] = precv[k] == SP2_PREC_FP64 ? 0.0 : e_noise(precv[k] == SP2_PREC_FP32 ? M_F32 : M_BF16X3, trv[k]);
+    homo_lumo(sch, e, trv, p, alph, n, lmin, lmax, N, n_occ, h, l, &noise);
   }
   double bound = NaN;
   if (sch.bounds) {
@@ -1159,6 +1365,10 @@ int Solver::finish(sp2_bsr **D_out, double *hest, double *lest, sp2_stats *st, s
   *D_out = export_bsr(c, X);
   X = DMat();
   busy_s += seconds_since(t0);
+  if (verbose())
+    std::fprintf(stderr, "[sp2] %.3f s in the library; device allocator: %lld allocations %.3f s, %lld frees %.3f s "
+                 "(context totals)\n", busy_s, (long long)c.n_raw_alloc, c.raw_alloc_s, (long long)c.n_raw_free,
+                 c.raw_free_s);
   if (hest) *hest = h;
   if (lest) *lest = l;
   if (st) {
@@ -1183,6 +1393,8 @@ int Solver::finish(sp2_bsr **D_out, double *hest, double *lest, sp2_stats *st, s
     st->corr_e_last = cs.e_last;
     st->corr_max_nnzb = cs.max_nnzb;
     st->seq_bytes = seq_bytes;
+    st->seq_host_bytes = host_bytes;
+    st->corr_recomputed = n_recomputed;
     st->device_peak_bytes = (int64_t)c.peak_bytes;
     for (int k = 0; k <= n; ++k) {
       if (st->square_time_s) st->square_time_s[k] = ksq[k];
@@ -1438,6 +1650,10 @@ void sp2_destroy(sp2_ctx *ctx) {
   if (!ctx) return;
   (void)hipSetDevice(ctx->device);
   (void)hipStreamSynchronize(ctx->stream);
+  if (ctx->copy_stream) {
+    (void)hipStreamSynchronize(ctx->copy_stream);
+    (void)hipStreamDestroy(ctx->copy_stream);
+  }
   ctx->trim();
   delete ctx;
 }

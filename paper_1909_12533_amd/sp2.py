@@ -170,7 +170,9 @@ class Context:
             pass
 
     def take(self, ptr):
-        """Copy a library-owned matrix into torch tensors and free it."""
+        """Copy a library-owned matrix into torch tensors and free it (the
+        library's cached buffers are released first, to make room)."""
+        self.lib.sp2_trim(self.h)
         m = ptr.contents
         n, nbr, nnzb = int(m.n), int(m.nbr), int(m.nnzb)
         row_ptr = torch.empty(nbr + 1, dtype=torch.int64, device=self.device)
@@ -353,6 +355,7 @@ class _Stats:
                              correction={k: getattr(st, k) for k in ("corr_rounds", "corr_time_s", "corr_flops",
                                                                      "corr_delta_norm", "corr_step_norm",
                                                                      "corr_e_last", "corr_max_nnzb", "seq_bytes",
+                                                                     "seq_host_bytes", "corr_recomputed",
                                                                      "device_peak_bytes")},
                              iters=iters, tape=Tape(ctx, tape_h) if record_tape else None)
 

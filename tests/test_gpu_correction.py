@@ -33,7 +33,9 @@ def test_fp64_correction_matches_oracle(gpu_lib):
     ref = O.sp2(Fd, no, lmin, lmax, -0.37, 0.34, keep_tape=True, **kw)
     Dref, inf = O.subspace_correction(Fd, ref.D, ref.X[: ref.n], ref.p, ref.alpha, lmin, lmax, beta=1e-9,
                                       tau_purify=ref.tau[ref.n], trunc_norm="frobinf", coarse_bs=128)
-    r = sp2.density(sp2.BsrMatrix.from_host(Fh), no, lmin, lmax, -0.37, 0.34, correct=1, corr_tol=1e-9, **kw)
+    # corr_deriv_tol 1e-300: every derivative step, as the oracle takes them
+    r = sp2.density(sp2.BsrMatrix.from_host(Fh), no, lmin, lmax, -0.37, 0.34, correct=1, corr_tol=1e-9,
+                    corr_deriv_tol=1e-300, **kw)
     assert r.n_iter == ref.n
     assert r.correction["corr_rounds"] == 1
     D = to_dense(r.D)
@@ -95,9 +97,11 @@ def test_low_precision_lattice_target(gpu_lib, prec, rounds):
     assert abs(np.trace(D) - no) <= 1e-6
 
 
-def test_recomputed_iterates_give_identical_result(gpu_lib):
-    """With no room for copies (corr_mem = 1 byte) the correction recomputes
-    X~_1 .. X~_{n-1} from the recorded masks and polynomials: bit-identical D."""
+def test_stored_and_recomputed_iterates_give_identical_result(gpu_lib):
+    """The correction's X~_1 .. X~_{n-1} kept on the device, copied to pinned
+    host memory and back on the copy stream (corr_mem = 1 byte), or recomputed
+    from the recorded masks and polynomials (no host memory either): the same
+    D bit for bit."""
     sp2 = gpu_lib
     Fh, info = lattice_fock(6, seed=0)
     Fd = bsr_to_dense(Fh)
@@ -107,6 +111,63 @@ def test_recomputed_iterates_give_identical_result(gpu_lib):
     kw = dict(trunc_norm="frobinf", tau_fixed=1e-5, coarse_bs=128, precision="bf16x3", switch_tol=0.0, correct=1)
     r1 = sp2.density(F, no, lmin, lmax, -0.37, 0.34, **kw)
     r2 = sp2.density(F, no, lmin, lmax, -0.37, 0.34, corr_mem=1, **kw)
-    assert r2.correction["seq_bytes"] < r1.correction["seq_bytes"]
-    assert np.array_equal(upper_mask(r1.D), upper_mask(r2.D))
-    assert np.array_equal(to_dense(r1.D), to_dense(r2.D))
+    r3 = sp2.density(F, no, lmin, lmax, -0.37, 0.34, corr_mem=1, corr_host_mem=-1, **kw)
+    c1, c2, c3 = r1.correction, r2.correction, r3.correction
+    print(c1, c2, c3, sep="\n")
+    assert c1["seq_host_bytes"] == 0 and c1["corr_recomputed"] == 0
+    assert c2["seq_bytes"] < c1["seq_bytes"] and c2["seq_host_bytes"] > 0 and c2["corr_recomputed"] == 0
+    assert c3["seq_host_bytes"] == 0 and c3["corr_recomputed"] > 0
+    for r in (r2, r3):
+        assert np.array_equal(upper_mask(r1.D), upper_mask(r.D))
+        assert np.array_equal(to_dense(r1.D), to_dense(r.D))
+
+
+def test_fp64_mcweeny_correction_matches_oracle(gpu_lib):
+    """FP64 expansion + correction with one McWeeny purification
+    (P' = P + R - (P R + R P), R = P^2 - P) equals the oracle's expansion +
+    ``subspace_correction(purify_form="mcweeny")`` block for block."""
+    sp2 = gpu_lib
+    Fh, info = lattice_fock(6, seed=0)
+    Fd = bsr_to_dense(Fh)
+    no = info["n_occ"]
+    lmin, lmax = O.gershgorin_bounds(Fd)
+    kw = dict(accel=True, trunc_norm="frobinf", tau_fixed=1e-4, coarse_bs=128)
+    ref = O.sp2(Fd, no, lmin, lmax, -0.37, 0.34, keep_tape=True, **kw)
+    Dref, inf = O.subspace_correction(Fd, ref.D, ref.X[: ref.n], ref.p, ref.alpha, lmin, lmax, beta=1e-9,
+                                      purify=1, purify_form="mcweeny", tau_purify=ref.tau[ref.n],
+                                      trunc_norm="frobinf", coarse_bs=128)
+    r = sp2.density(sp2.BsrMatrix.from_host(Fh), no, lmin, lmax, -0.37, 0.34, correct=1, corr_tol=1e-9,
+                    corr_mcweeny=1, corr_purify=1, corr_deriv_tol=1e-300, **kw)
+    D = to_dense(r.D)
+    print(f"max |D - D_oracle| = {np.max(np.abs(D - Dref)):.3e}")
+    assert r.n_iter == ref.n
+    assert np.array_equal(upper_mask(r.D), np.triu(O.structural_mask(Dref, 64) | np.eye(Fh.nbr, dtype=bool)))
+    assert np.max(np.abs(D - Dref)) <= 1e-10
+    assert r.correction["corr_step_norm"] == pytest.approx(inf["step_norm"], rel=1e-8)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_mcweeny_low_precision_lattice_target(gpu_lib, prec):
+    """Lattice 8 x 8 x 8 x 4, tau = 1e-6: the low-precision expansion with the
+    correction and one McWeeny purification (its cubic term in the low
+    arithmetic) lands within 1e-5 of the FP64 expansion, as the two-square
+    purification does."""
+    sp2 = gpu_lib
+    Fh, info = lattice_fock(8, seed=0)
+    Fd = bsr_to_dense(Fh)
+    no = info["n_occ"]
+    lam, Dst = _exact(Fd, no)
+    lmin, lmax = O.gershgorin_bounds(Fd)
+    gap = lam[no] - lam[no - 1]
+    h, lu = lam[no - 1] + 0.01 * gap, lam[no] - 0.01 * gap
+    F = sp2.BsrMatrix.from_host(Fh)
+    kw = dict(trunc_norm="frobinf", tau_fixed=1e-6, coarse_bs=512)
+    r64 = sp2.density(F, no, lmin, lmax, h, lu, **kw)
+    r = sp2.density(F, no, lmin, lmax, h, lu, precision=prec, switch_tol=0.0, correct=1, corr_mcweeny=1,
+                    corr_purify=1, **kw)
+    D64, D = to_dense(r64.D), to_dense(r.D)
+    e_ref = np.linalg.norm(D - D64)
+    print(f"{prec} + McWeeny: ||D - D_fp64||_F = {e_ref:.3e}, ||D^2 - D|| = {np.linalg.norm(D @ D - D):.3e}")
+    assert e_ref <= 1e-5
+    assert np.linalg.norm(D @ D - D) <= 1e-6
+    assert abs(np.trace(D) - no) <= 1e-6

@@ -91,3 +91,26 @@ def test_block_dropping_budget(case):
     D1 = _rotated(Dst, 1e-3, seed=4)
     D, _ = O.subspace_correction(F, D1, r.X[: r.n], r.p, r.alpha, r.lmin, r.lmax, beta=1e-8)
     assert np.linalg.norm(D - Dst) <= 1e-2 * np.linalg.norm(D1 - Dst)
+
+
+def test_mcweeny_purification_closed_form():
+    """One McWeeny purification step maps every eigenvalue x of a symmetric P
+    to 3x^2 - 2x^3 and keeps the eigenvectors: with Delta = 0 (P commutes with
+    F) the correction reduces to that step, checked against the spectral
+    formula on P = Q diag(x) Q^T."""
+    n = 128
+    rng = np.random.default_rng(11)
+    Q, R = np.linalg.qr(rng.standard_normal((n, n)))
+    Q = Q * np.sign(np.diag(R))
+    x = np.concatenate([1.0 - rng.uniform(0, 0.05, n // 2), rng.uniform(0, 0.05, n - n // 2)])
+    lam = np.where(x > 0.5, -1.0, 1.0) * np.linspace(0.2, 1.0, n)
+    F = (Q * lam) @ Q.T
+    F = 0.5 * (F + F.T)
+    P = (Q * x) @ Q.T
+    P = 0.5 * (P + P.T)
+    D, _ = O.subspace_correction(F, P, [], [-1], [1.0], -1.0, 1.0, purify=1, purify_form="mcweeny")
+    want = (Q * (3 * x ** 2 - 2 * x ** 3)) @ Q.T
+    assert np.linalg.norm(D - want) <= 1e-13 * np.sqrt(n)
+    # the SP2 pair x^2 then 2x - x^2 is a different polynomial (x^2 (2 - x^2))
+    D2, _ = O.subspace_correction(F, P, [], [-1], [1.0], -1.0, 1.0, purify=2)
+    assert np.linalg.norm(D2 - (Q * (x ** 2 * (2 - x ** 2))) @ Q.T) <= 1e-13 * np.sqrt(n)
