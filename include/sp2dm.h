@@ -395,6 +395,18 @@ int sp2_truncate(sp2_ctx *ctx, const sp2_bsr *X, double tau, int norm, int64_t c
  * FP64 in a fixed order (bitwise reproducible). */
 int sp2_matrix_norms(sp2_ctx *ctx, const sp2_bsr *A, int64_t coarse_bs, double *frob, double *frobinf);
 
+/* sp2_matrix_norms without any device allocation, for callers that cannot
+ * allocate (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, kernels and results (bit for bit) as
+ * sp2_matrix_norms; its block norms, row indices, flags and partial sums live
+ * in a fixed device scratch array of 64 MiB that every device the library
+ * runs on holds until the process ends.  A matrix needing more scratch than
+ * that (about 5.5 million stored blocks) is rejected with
+ * SP2_ERR_INVALID_ARG before any device work.  Every call on a device shares
+ * that device's array: calls that overlap on one device (other host threads,
+ * other contexts) race and must be serialised by the caller. */
+int sp2_matrix_norms_noalloc(sp2_ctx *ctx, const sp2_bsr *A, int64_t coarse_bs, double *frob, double *frobinf);
+
 /* Copy a library matrix into caller buffers (device pointers of sizes
  * nbr + 1, nnzb, nnzb * 64 * 64). */
 int sp2_bsr_copy(sp2_ctx *ctx, const sp2_bsr *src, int64_t *row_ptr, int32_t *col_idx, double *val);

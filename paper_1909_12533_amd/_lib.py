@@ -26,7 +26,7 @@ EXPORTS = [
     "sp2_last_error", "sp2_gershgorin", "sp2_density", "sp2_vjp", "sp2_jvp", "sp2_replay", "sp2_tape_info",
     "sp2_square_step", "sp2_truncate", "sp2_bsr_copy", "sp2_bsr_free", "sp2_tape_free", "sp2_schedule",
     "sp2_homo_lumo", "sp2_pair_product", "sp2_matrix_norms", "sp2_density_begin", "sp2_density_step",
-    "sp2_density_end", "sp2_solver_free",
+    "sp2_density_end", "sp2_solver_free", "sp2_matrix_norms_noalloc",
 ]
 
 
@@ -193,6 +193,8 @@ def load(path: str = LIB_PATH):
                                  P(C.c_double)]
     lib.sp2_matrix_norms.restype = C.c_int
     lib.sp2_matrix_norms.argtypes = [C.c_void_p, P(sp2_bsr), C.c_int64, P(C.c_double), P(C.c_double)]
+    lib.sp2_matrix_norms_noalloc.restype = C.c_int
+    lib.sp2_matrix_norms_noalloc.argtypes = [C.c_void_p, P(sp2_bsr), C.c_int64, P(C.c_double), P(C.c_double)]
     lib.sp2_bsr_copy.restype = C.c_int
     lib.sp2_bsr_copy.argtypes = [C.c_void_p, P(sp2_bsr), C.c_void_p, C.c_void_p, C.c_void_p]
     lib.sp2_bsr_free.restype = None

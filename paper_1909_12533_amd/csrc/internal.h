@@ -92,6 +92,9 @@ struct Ctx {
   double *h_pinned = nullptr;  // pinned host staging for small device->host reads
   size_t h_pinned_bytes = 0;
 
+  // device address of the no-allocation entry point's scratch array on this
+  // context's device (set by sp2_create)
+  void *scratch = nullptr;
   // second stream (default priority) for host <-> device copies that overlap
   // the kernels of `stream`; created on first use
   hipStream_t copy_stream = nullptr;

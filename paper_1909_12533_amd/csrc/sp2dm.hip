@@ -15,6 +15,7 @@
 
 #include <chrono>
 #include <map>
+#include <mutex>
 #include <cstdlib>
 #include <cmath>
 #include <cstdio>
@@ -1602,6 +1603,46 @@ template <typename Fn> int guarded(sp2_ctx *ctx, Fn &&fn) {
 }  // namespace
 }  // namespace sp2
 
+// ================================================= no-allocation scratch
+// Device scratch of sp2_matrix_norms_noalloc: block norms, row indices,
+// flags and partial sums live here instead of in allocated buffers.  Every
+// device the library runs on holds its own copy for the life of the process;
+// host code reaches it only through the address hipGetSymbolAddress returns
+// for that device (the array's name in host code is not a device address).
+namespace sp2 {
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)64 << 20;
+constexpr int MAX_DEVICES = 64;
+}  // namespace sp2
+
+static __device__ __align__(256) unsigned char scratch[sp2::NOALLOC_SCRATCH_BYTES];
+
+namespace sp2 {
+namespace {
+
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[MAX_DEVICES] = {};
+
+// device address of `scratch` on `device`, looked up once per device with that
+// device current (sp2_create has made it current)
+void *scratch_setup(int device) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (device < 0 || device >= MAX_DEVICES) return nullptr;
+  if (!g_scratch_ptr[device]) {
+    void *ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    g_scratch_ptr[device] = ptr;
+  }
+  return g_scratch_ptr[device];
+}
+
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+}  // namespace
+}  // namespace sp2
+
 // ====================================================================== C ABI
 using namespace sp2;
 
@@ -1639,8 +1680,11 @@ int sp2_create(sp2_ctx **ctx, int device, void *hip_stream) {
     return SP2_ERR_HIP;
   }
   if (hipSetDevice(device) != hipSuccess) return SP2_ERR_HIP;
+  void *scr = scratch_setup(device);
+  if (!scr) return SP2_ERR_HIP;
   auto *c = new sp2_ctx();
   c->device = device;
+  c->scratch = scr;
   c->stream = static_cast<hipStream_t>(hip_stream);
   *ctx = c;
   return SP2_OK;
@@ -1968,6 +2012,89 @@ int sp2_matrix_norms(sp2_ctx *ctx, const sp2_bsr *Ain, int64_t coarse_bs, double
                               cb, nc, pair.as<double>(), rows.as<double>());
         std::vector<double> h(nc);
         ctx->d2h(h.data(), rows.p, sizeof(double) * nc);
+        for (double v : h) *frobinf = std::max(*frobinf, v);
+      }
+    }
+    return SP2_OK;
+  });
+}
+
+int sp2_matrix_norms_noalloc(sp2_ctx *ctx, const sp2_bsr *Ain, int64_t coarse_bs, double *frob, double *frobinf) {
+  return guarded(ctx, [&]() {
+    Ctx &c = *ctx;
+    if (!c.scratch) fail(SP2_ERR_HIP, "device scratch of the no-allocation entry point is not set up");
+    if (frobinf && (coarse_bs <= 0 || coarse_bs % B))
+      fail(SP2_ERR_INVALID_ARG, "coarse_bs must be a positive multiple of 64");
+    check_input(Ain, "A");
+    const int64_t nnzb = Ain->nnzb;
+    const int nbr = (int)Ain->nbr, cb = frobinf ? (int)(coarse_bs / B) : 1;
+    const int nc = frobinf ? (nbr + cb - 1) / cb : 0;
+    if (nc > 16384) fail(SP2_ERR_INVALID_ARG, "coarse_bs too small for this matrix (more than 16384 submatrices per row)");
+    const int64_t npairs = (int64_t)nc * (nc + 1) / 2;
+    // scratch layout: row of each block, block norms, flag, sum, reduction
+    // stage, coarse pair sums, coarse row sums
+    const size_t nb = (size_t)std::max<int64_t>(nnzb, 1);
+    size_t off = 0;
+    const size_t o_row = off;
+    off += align256(sizeof(int32_t) * nb);
+    const size_t o_nrm = off;
+    off += align256(sizeof(double) * nb);
+    const size_t o_flag = off;
+    off += 256;
+    const size_t o_sum = off;
+    off += 256;
+    const size_t o_stage = off;
+    off += align256(sizeof(double) * (size_t)reduce_stage_doubles(1));
+    const size_t o_pair = off;
+    off += align256(sizeof(double) * (size_t)std::max<int64_t>(npairs, 1));
+    const size_t o_rows = off;
+    off += align256(sizeof(double) * (size_t)std::max(nc, 1));
+    if (off > NOALLOC_SCRATCH_BYTES)
+      fail(SP2_ERR_INVALID_ARG, "matrix too large for sp2_matrix_norms_noalloc: needs " + std::to_string(off) +
+                                    " bytes of device scratch, the maximum is " +
+                                    std::to_string(NOALLOC_SCRATCH_BYTES) + " (about 5.5 million stored blocks)");
+    char *sc = static_cast<char *>(c.scratch);
+    int32_t *row_of = reinterpret_cast<int32_t *>(sc + o_row);
+    double *nrm2 = reinterpret_cast<double *>(sc + o_nrm);
+    int32_t *flag = reinterpret_cast<int32_t *>(sc + o_flag);
+    double *sum = reinterpret_cast<double *>(sc + o_sum);
+    double *stage = reinterpret_cast<double *>(sc + o_stage);
+    double *pair = reinterpret_cast<double *>(sc + o_pair);
+    double *rows = reinterpret_cast<double *>(sc + o_rows);
+    // the pattern and value checks of sp2_matrix_norms
+    std::vector<int64_t> rp(nbr + 1);
+    c.d2h(rp.data(), Ain->row_ptr, sizeof(int64_t) * (nbr + 1));
+    if (rp[0] != 0 || rp[nbr] != nnzb) fail(SP2_ERR_INVALID_ARG, "A: row_ptr ends");
+    for (int r = 0; r < nbr; ++r)
+      if (rp[r + 1] < rp[r]) fail(SP2_ERR_INVALID_ARG, "A: row_ptr not monotone");
+    int32_t f = 0;
+    launch_row_of(c, Ain->row_ptr, nbr, row_of);
+    launch_fill_i32(c, flag, 1, 0);
+    launch_validate_pattern(c, Ain->row_ptr, Ain->col_idx, nbr, nnzb, flag);
+    c.d2h(&f, flag, sizeof(f));
+    if (f) fail(SP2_ERR_INVALID_ARG, "A: columns must satisfy row <= col < nbr, strictly increasing");
+    launch_fill_i32(c, flag, 1, 0);
+    launch_check_finite(c, Ain->val, nnzb * (int64_t)BB, flag);
+    c.d2h(&f, flag, sizeof(f));
+    if (f) fail(SP2_ERR_NONFINITE, "A holds non-finite values");
+    if (frob) {
+      *frob = 0.0;
+      if (nnzb > 0) {
+        launch_block_norms(c, Ain->val, P64, nullptr, nnzb, nrm2);
+        launch_weight_offdiag(c, nrm2, row_of, Ain->col_idx, nnzb);
+        launch_reduce_parts(c, nrm2, nnzb, 1, sum, stage);
+        double v = 0.0;
+        c.d2h(&v, sum, sizeof(double));
+        *frob = std::sqrt(std::fmax(v, 0.0));
+      }
+    }
+    if (frobinf) {
+      *frobinf = 0.0;
+      if (nnzb > 0 && nc > 0) {
+        launch_block_norms(c, Ain->val, P64, nullptr, nnzb, nrm2);
+        launch_coarse_rowsums(c, Ain->row_ptr, Ain->col_idx, nrm2, nbr, cb, nc, pair, rows);
+        std::vector<double> h(nc);
+        c.d2h(h.data(), rows, sizeof(double) * nc);
         for (double v : h) *frobinf = std::max(*frobinf, v);
       }
     }

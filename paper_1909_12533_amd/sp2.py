@@ -482,6 +482,16 @@ def matrix_norms(A: BsrMatrix, coarse_bs=4096, ctx: Context | None = None):
     return f.value, m.value
 
 
+def matrix_norms_noalloc(A: BsrMatrix, coarse_bs=4096, ctx: Context | None = None):
+    """matrix_norms through sp2_matrix_norms_noalloc: no device allocation,
+    the library's fixed device scratch array instead."""
+    ctx = ctx or context(A.device.index)
+    f, m = C.c_double(), C.c_double()
+    s = A._struct()
+    ctx._check(ctx.lib.sp2_matrix_norms_noalloc(ctx.h, C.byref(s), int(coarse_bs), C.byref(f), C.byref(m)))
+    return f.value, m.value
+
+
 def truncate(X: BsrMatrix, tau: float, norm="frobinf", coarse_bs=4096, ctx: Context | None = None):
     """Truncation with ||E|| <= tau; returns (X~, (||E||_F, ||E||_M))."""
     ctx = ctx or context(X.device.index)
