@@ -521,7 +521,14 @@ def main():
     code = {"fp64": 0, "fp32": 1, "bf16x3": 2}[prec]
     k_fl = sum(r["kernel_flops"][code] for r in timed)
     k_s = sum(r["kernel_s"][code] for r in timed)
+    k_n = sum(r["kernel_launches"][code] for r in timed)
     achieved = k_fl / k_s / 1e12 if k_s > 0 else 0.0
+    # the same kernels over the whole first solve (the launches a kernel trace of
+    # this command lists for the timed path), by arithmetic
+    solve_kernels = {name: {"launches": sum(r["kernel_launches"][c] for r in first),
+                            "device_s": round(sum(r["kernel_s"][c] for r in first), 4),
+                            "alg_tflop": round(sum(r["kernel_flops"][c] for r in first) / 1e12, 3)}
+                     for c, name in enumerate(("fp64", "fp32", "bf16x3"))}
     D = res.D
     checks = {"status": res.status, "stop": res.stop_reason, "n_iter": res.n_iter,
               "trace_err": abs(trace_of(D) - no), "e_n": float(res.iters["e"][-1]),
@@ -580,7 +587,9 @@ def main():
         "checks": checks,
         "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK[prec], "unit": "TFLOP/s",
                      "frac": round(achieved / PEAK[prec], 4), "traffic": traffic_per_launch(prec, L),
-                     "kernel": f"{KERNELS[prec][0]} ({prec.upper()} MFMA block products, timed steps)"},
+                     "kernel": f"{KERNELS[prec][0]} ({prec.upper()} MFMA block products, timed steps)",
+                     "timed_launches": k_n, "avg_launch_ms": round(1e3 * k_s / max(k_n, 1), 3),
+                     "solve_kernels": solve_kernels},
     }
     if run1:
         line["config"]["run1"] = run1

@@ -295,6 +295,7 @@ typedef struct {
                              from HIP events on the context stream */
   double kernel_flops[3]; /* algorithmic flops of those launches, same index (a recomputed iterate's
                              square counts here but not in flops) */
+  int32_t kernel_launches[3]; /* number of those launches, same index */
 } sp2_step_info;
 int sp2_density_begin(sp2_ctx *ctx, const sp2_bsr *F, int64_t n_occ, double lmin, double lmax,
                       const double *homo_ub, const double *lumo_lb, const sp2_options *opt, sp2_solver **solver);

@@ -127,6 +127,7 @@ class sp2_step_info(C.Structure):
         ("wall_s", C.c_double),
         ("kernel_s", C.c_double * 3),
         ("kernel_flops", C.c_double * 3),
+        ("kernel_launches", C.c_int32 * 3),
     ]
 
 

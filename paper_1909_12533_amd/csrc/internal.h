@@ -86,6 +86,7 @@ struct Ctx {
   // launched so far, by arithmetic (Mode); read by the stepped solver
   double kern_s[3] = {0.0, 0.0, 0.0};
   double kern_flops[3] = {0.0, 0.0, 0.0};
+  int64_t kern_launches[3] = {0, 0, 0};
   // calls into the device allocator and the host time they took
   int64_t n_raw_alloc = 0, n_raw_free = 0;
   double raw_alloc_s = 0.0, raw_free_s = 0.0;

@@ -284,6 +284,7 @@ struct SquareOut {
   Buf parts;      // nout x NPART
   double sums[NPART];
   double kernel_s = 0.0;  // device time of the MFMA square (HIP events)
+  double plan_s = 0.0;    // with SP2_VERBOSE: wall time of planning, allocation and packing before the kernel
 };
 
 struct EventPair {
@@ -299,6 +300,7 @@ struct EventPair {
 };
 
 SquareOut square_step(Ctx &c, const DMat &X, const Maps &m, int mode, int oprec, double ca, double cb, double cc) {
+  const auto t0 = std::chrono::steady_clock::now();
   SquareOut r;
   r.next.pat = symbolic_square(c, X.pat, m);
   const int64_t nout = r.next.pat.nnzb;
@@ -337,6 +339,10 @@ SquareOut square_step(Ctx &c, const DMat &X, const Maps &m, int mode, int oprec,
   ta.n = X.pat.n;
   ta.parts = r.parts.as<double>();
   EventPair ev;
+  if (verbose()) {
+    c.sync();
+    r.plan_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
   SP2_HIP(hipEventRecord(ev.a, c.stream));
   if (mode == M_F64 && oprec == P64 && ta.xprec == P64 && tb == 2 && use_f64_lds())
     launch_square_f64_lds(c, ta);
@@ -351,6 +357,7 @@ SquareOut square_step(Ctx &c, const DMat &X, const Maps &m, int mode, int oprec,
   r.kernel_s = 1e-3 * (double)ms;
   c.kern_s[mode] += r.kernel_s;
   c.kern_flops[mode] += r.sums[4] * 2.0 * B * B * B;
+  if (nout > 0) c.kern_launches[mode]++;
   return r;
 }
 
@@ -369,6 +376,7 @@ struct PairOpt {
 // values in the precision the mode multiplies (FP64 or FP32); the maps need
 // adjacency lists when the output pattern is the product's own.
 SquareOut pair_product(Ctx &c, const DMat &X, const Maps &mx, const DMat &Y, const Maps &my, const PairOpt &po) {
+  const auto t0 = std::chrono::steady_clock::now();
   const int need = po.mode == M_F64 ? P64 : P32;
   if (po.mode == M_F64 && po.oprec == P32 && po.G) fail(SP2_ERR_INVALID_ARG, "pair product: FP32 output takes no G");
   if (X.pool->prec != need || Y.pool->prec != need || (po.G && po.G->pool->prec != need))
@@ -420,6 +428,10 @@ SquareOut pair_product(Ctx &c, const DMat &X, const Maps &mx, const DMat &Y, con
   ta.n = X.pat.n;
   ta.parts = r.parts.as<double>();
   EventPair ev;
+  if (verbose()) {
+    c.sync();
+    r.plan_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
   SP2_HIP(hipEventRecord(ev.a, c.stream));
   if (po.mode == M_F64 && tb == 2 && use_f64_lds())
     launch_square_f64_lds(c, ta);
@@ -434,6 +446,7 @@ SquareOut pair_product(Ctx &c, const DMat &X, const Maps &mx, const DMat &Y, con
   r.kernel_s = 1e-3 * (double)ms;
   c.kern_s[po.mode] += r.kernel_s;
   c.kern_flops[po.mode] += r.sums[4] * 2.0 * B * B * B;
+  if (nout > 0) c.kern_launches[po.mode]++;
   return r;
 }
 
@@ -1160,6 +1173,7 @@ void Solver::correct_step() {
     case C_DERIV: {
       // derivative of X_{k+1} = ca I + cb X~_k + cc X~_k^2 along dX~_k
       const int k = ck;
+      const auto t_step = std::chrono::steady_clock::now();
       TapeIter &tk = ct.it[k];
       const char *src = "";
       if (tk.ckpt) {
@@ -1178,6 +1192,8 @@ void Solver::correct_step() {
         ++n_recomputed;
         src = " (recomputed iterate)";
       }
+      if (verbose()) c.sync();
+      const double t_it = seconds_since(t_step);
       if (cround == o.correct - 1) {  // the last round needs X~_k only here
         tk.ckpt.reset();
         tk.hcopy.reset();
@@ -1204,8 +1220,9 @@ void Solver::correct_step() {
       dX = std::move(jo.next);
       drop(dX, jo);
       if (verbose())
-        std::fprintf(stderr, "[sp2] correction: derivative step %d/%d nnzb=%lld%s product %.1f ms\n", k + 1,
-                     n_deriv, (long long)dX.pat.nnzb, src, 1e3 * jo.kernel_s);
+        std::fprintf(stderr, "[sp2] correction: derivative step %d/%d nnzb=%lld%s product %.1f ms (planning %.1f ms), "
+                     "iterate %.1f ms, step %.1f ms\n", k + 1, n_deriv, (long long)dX.pat.nnzb, src, 1e3 * jo.kernel_s,
+                     1e3 * jo.plan_s, 1e3 * t_it, 1e3 * seconds_since(t_step));
       ++ck;
       break;
     }
@@ -1300,9 +1317,11 @@ bool Solver::step() {
   if (phase == FAILED) fail(SP2_ERR_INVALID_ARG, "an earlier step failed; release the solver");
   auto t0 = std::chrono::steady_clock::now();
   double ks0[3], kf0[3];
+  int64_t kl0[3];
   for (int m = 0; m < 3; ++m) {
     ks0[m] = c.kern_s[m];
     kf0[m] = c.kern_flops[m];
+    kl0[m] = c.kern_launches[m];
   }
   const bool expanding = phase == EXPAND;
   const int it0 = i;
@@ -1327,6 +1346,7 @@ bool Solver::step() {
   for (int m = 0; m < 3; ++m) {
     info.kernel_s[m] = c.kern_s[m] - ks0[m];
     info.kernel_flops[m] = c.kern_flops[m] - kf0[m];
+    info.kernel_launches[m] = (int32_t)(c.kern_launches[m] - kl0[m]);
     if (info.kernel_flops[m] > info.kernel_flops[dom]) dom = m;
   }
   info.precision = dom == M_F64 ? SP2_PREC_FP64 : (dom == M_F32 ? SP2_PREC_FP32 : SP2_PREC_BF16X3);

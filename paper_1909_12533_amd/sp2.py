@@ -412,7 +412,7 @@ class Solver:
         return {"done": self.done, "kind": {L.STEP_ITERATION: "iteration", L.STEP_CORRECTION: "correction"}[info.kind],
                 "iteration": int(info.iteration), "precision": _PREC_NAME[int(info.precision)],
                 "flops": float(info.flops), "wall_s": float(info.wall_s), "kernel_s": list(info.kernel_s),
-                "kernel_flops": list(info.kernel_flops)}
+                "kernel_flops": list(info.kernel_flops), "kernel_launches": list(info.kernel_launches)}
 
     def end(self) -> DensityResult:
         sts = _Stats(self.o.n_max_cap)
