@@ -17,7 +17,10 @@ the density matrix with error control on distributed computer systems"
 * the Frobenius and Frob-Inf truncation norms (section "Upper bounds for the
   spectral norm");
 * beyond the paper, for low-precision expansions: the first-order correction
-  of the occupied subspace, ``subspace_correction``.
+  of the occupied subspace, ``subspace_correction``;
+* the product of matrices in general (full-pattern) storage, the format of the
+  paper's general matrix wrapper (section "Implementation details"),
+  ``general_product``.
 
 Matrices are stored dense in float64, with a symmetric boolean block mask
 (nbr x nbr, block size ``bs``) that records which blocks are structurally
@@ -806,6 +809,49 @@ def subspace_correction(F, D, X_seq, p, alpha, lmin, lmax, *, rounds=1, purify=2
             P, M, _ = truncate(X, MX, tau_purify, trunc_norm, bs, coarse_bs)
         D = P
     return D, info
+
+
+# ==========================================================================
+# general (full-pattern) storage
+# ==========================================================================
+
+def general_pattern(MA, MB, MG=None, diag=False):
+    """Block pattern of a product A B of general (not necessarily symmetric)
+    matrices: (I, J) is present when some K has A's block (I, K) and B's block
+    (K, J) present.  The pattern MG of an added matrix and, with ``diag``, the
+    diagonal blocks are joined to it."""
+    P = (np.asarray(MA, dtype=np.int64) @ np.asarray(MB, dtype=np.int64)) > 0
+    if MG is not None:
+        P = P | np.asarray(MG, dtype=bool)
+    if diag:
+        P = P | np.eye(P.shape[0], dtype=bool)
+    return P
+
+
+def general_product(A, MA, B, MB, G=None, MG=None, a=0.0, b=0.0, c=1.0, bs=BS):
+    """out = a I + b G + c A B on the block pattern of ``general_pattern``
+    (the diagonal joined when a != 0), for matrices in general storage (every
+    present block of both triangles stored; the general matrix wrapper of
+    section "Implementation details", which section "Numerical experiments"
+    compares with the symmetric one).  A, B, G are dense; MA, MB, MG their
+    block masks (blocks outside a mask are taken as zero).  Returns
+    (out, P, sums) with sums = [||G - A B||_F^2, tr G, tr(A B), flops], where
+    flops = 2 bs^3 per block triple (I, K, J) with (I, K) in MA and (K, J) in
+    MB."""
+    A = np.asarray(A, dtype=np.float64)
+    n = A.shape[0]
+    Am = A * expand_mask(MA, n, bs)
+    Bm = np.asarray(B, dtype=np.float64) * expand_mask(MB, n, bs)
+    if G is None:
+        Gm = np.zeros((n, n))
+    else:
+        Gm = np.asarray(G, dtype=np.float64) * expand_mask(MG, n, bs)
+    P = general_pattern(MA, MB, MG if G is not None else None, diag=(a != 0.0))
+    S = Am @ Bm
+    out = (a * np.eye(n) + b * Gm + c * S) * expand_mask(P, n, bs)
+    triples = int((np.asarray(MA, dtype=np.int64) @ np.asarray(MB, dtype=np.int64)).sum())
+    sums = [frobenius_norm(Gm - S) ** 2, float(np.trace(Gm)), float(np.trace(S)), 2.0 * bs ** 3 * triples]
+    return out, P, sums
 
 
 # ==========================================================================
