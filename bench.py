@@ -198,10 +198,14 @@ def adjoint_bench(sp2, F, Fh, no, lmin, lmax, hub, llb, opts, precisions):
     out = {}
     ref = {}
     for label in precisions:
-        prec, _, adj = label.partition("/")
+        head, *extra = label.split("@")
+        prec, _, adj = head.partition("/")
         mo = dict(precision=prec, switch_tol=1e-3) if prec != "fp64" else {}
         if adj:
             mo["adjoint_precision"] = adj
+        for kv in extra:  # "@low_start_xi=0.3", "@switch_tol=1e-2"
+            k, _, v = kv.partition("=")
+            mo[k] = float(v)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         r = sp2.density(F, no, lmin, lmax, hub, llb, record_tape=True, **mo, **opts)
@@ -218,7 +222,10 @@ def adjoint_bench(sp2, F, Fh, no, lmin, lmax, hub, llb, opts, precisions):
         t_jvp = time.perf_counter() - t0
         rec = {"n_iter": r.n_iter, "forward_s": round(t_fwd, 4), "vjp_s": round(t_vjp, 4), "jvp_s": round(t_jvp, 4),
                "n_checkpoints": info["n_checkpoints"], "tape_device_bytes": info["device_bytes"],
-               "forward_device_peak_bytes": r.correction["device_peak_bytes"]}
+               "forward_device_peak_bytes": r.correction["device_peak_bytes"],
+               "square_precisions": "".join("dsb"[int(k)] for k in r.iters["precision"]),
+               "flops_low_frac": float(sum(f for f, k in zip(r.iters["iter_flops"], r.iters["precision"]) if k != 0)
+                                       / max(sum(r.iters["iter_flops"]), 1.0))}
         lhs, rhs = bsr_inner(W, jv), bsr_inner(g, dF)
         rec["dot_test_rel"] = abs(lhs - rhs) / max(abs(lhs), 1e-300)
         if prec == "fp64":
@@ -246,31 +253,73 @@ def adjoint_bench(sp2, F, Fh, no, lmin, lmax, hub, llb, opts, precisions):
 
 def storage_bench(sp2, F, no, lmin, lmax, hub, llb, opts, prec):
     """Symmetric vs general storage (the paper's comparison of its symmetric
-    and general matrix wrappers): D^2 of the converged density matrix by the
-    symmetric square (upper output blocks only) and by the two-operand product
-    D D + D D with c = 1/2, which performs the block multiplications of a
-    general product (every output block of both triangles, as a general
-    wrapper would); wall time of each call after one untimed call."""
+    and general matrix wrappers, section "Numerical experiments"): the
+    workload's expansion is run square by square (the FP64 run's polynomials
+    and thresholds); every X~_i is squared both by the symmetric square
+    (upper blocks stored and computed) and, after conversion to general
+    storage, by the general product a I + b X + c X X (every block of both
+    triangles stored and computed).  Reports per-iteration wall time of each
+    call (synchronized, planning and allocation included), stored blocks and
+    block products, and the totals over the run."""
+    import numpy as np
     import torch
 
-    D = sp2.density(F, no, lmin, lmax, hub, llb, **opts).D
-    out = {"nnzb_D": D.nnzb, "precision": prec}
-    for name, fn in (("symmetric_square", lambda: sp2.square_step(D, 0.0, 0.0, 1.0, prec)),
-                     ("general_product", lambda: sp2.pair_product(D, D, sign=1, c=0.5, precision=prec))):
-        fn()
+    ref = sp2.density(F, no, lmin, lmax, hub, llb, **opts)
+    it = ref.iters
+    n = ref.n_iter
+    w = lmax - lmin
+    # X~_0 = (lmax I - F) / w on F's pattern, truncated with tau_0
+    val = (-F.val / w).contiguous()
+    rp = F.row_ptr.cpu().numpy()
+    ci = F.col_idx.cpu().numpy()
+    diag = np.nonzero(ci == np.repeat(np.arange(len(rp) - 1), np.diff(rp)))[0]
+    nreal = F.n
+    for k, I in zip(diag, range(len(diag))):
+        m = min(64, nreal - 64 * I)
+        idx = torch.arange(m, device=val.device)
+        val[int(k), idx, idx] += lmax / w
+    X = sp2.BsrMatrix(F.n, F.row_ptr, F.col_idx, val)
+    X, _ = sp2.truncate(X, float(it["tau"][0]), opts["trunc_norm"], opts["coarse_bs"])
+    rows = []
+    tot = {"symmetric_s": 0.0, "general_s": 0.0, "convert_s": 0.0, "symmetric_flop": 0.0, "general_flop": 0.0}
+    for i in range(1, n + 1):
+        p, al = int(it["p"][i]), float(it["alpha"][i])
+        a, b, c = ((1 - al) ** 2, 2 * al * (1 - al), al * al) if p == 1 else (0.0, 2 * al, -al * al)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        r, sums = fn()
+        Y, ss = sp2.square_step(X, a, b, c, prec)
         torch.cuda.synchronize()
-        out[name + "_s"] = time.perf_counter() - t0
-        out[name + "_tflop"] = (sums[3] if len(sums) == 4 else sums[1]) / 1e12
-        out[name + "_result"] = r
-    a, b = out.pop("symmetric_square_result"), out.pop("general_product_result")
-    out["max_abs_diff"] = float((a.val - b.val).abs().max()) if a.nnzb == b.nnzb else None
-    out["time_ratio"] = out["general_product_s"] / out["symmetric_square_s"]
-    log(f"storage: symmetric {out['symmetric_square_s']:.3f} s ({out['symmetric_square_tflop']:.1f} TF), general "
-        f"{out['general_product_s']:.3f} s ({out['general_product_tflop']:.1f} TF), ratio {out['time_ratio']:.2f}, "
-        f"max |diff| {out['max_abs_diff']}")
+        t_sym = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        Xg = sp2.general_from_upper(X)
+        torch.cuda.synchronize()
+        t_conv = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        Yg, gs = sp2.general_product(Xg, Xg, Xg, a, b, c, prec)
+        torch.cuda.synchronize()
+        t_gen = time.perf_counter() - t0
+        row = {"i": i - 1, "nnzb_sym": X.nnzb, "nnzb_general": Xg.nnzb, "out_nnzb_sym": Y.nnzb,
+               "out_nnzb_general": Yg.nnzb, "symmetric_s": round(t_sym, 4), "general_s": round(t_gen, 4),
+               "convert_s": round(t_conv, 4), "symmetric_tflop": ss[3] / 1e12, "general_tflop": gs[3] / 1e12,
+               "e_rel_diff": abs(math.sqrt(max(gs[0], 0.0)) - math.sqrt(max(ss[0], 0.0))) / max(math.sqrt(ss[0]),
+                                                                                                  1e-300)}
+        rows.append(row)
+        tot["symmetric_s"] += t_sym
+        tot["general_s"] += t_gen
+        tot["convert_s"] += t_conv
+        tot["symmetric_flop"] += ss[3]
+        tot["general_flop"] += gs[3]
+        log(f"storage iter {i - 1}: {row}")
+        del Xg, Yg
+        X, _ = sp2.truncate(Y, float(it["tau"][i]), opts["trunc_norm"], opts["coarse_bs"])
+        del Y
+    out = {"precision": prec, "n_iter": n, "iterations": rows, **{k: round(v, 4) if k.endswith("_s") else v
+                                                                   for k, v in tot.items()}}
+    out["time_ratio"] = tot["general_s"] / tot["symmetric_s"]
+    out["flop_ratio"] = tot["general_flop"] / tot["symmetric_flop"]
+    out["stored_ratio_last"] = rows[-1]["nnzb_general"] / rows[-1]["nnzb_sym"]
+    log(f"storage: symmetric {tot['symmetric_s']:.3f} s, general {tot['general_s']:.3f} s "
+        f"(ratio {out['time_ratio']:.2f}, flops ratio {out['flop_ratio']:.2f}), conversion {tot['convert_s']:.3f} s")
     return out
 
 
@@ -409,12 +458,18 @@ def main():
                     help="1 (default): purify with one McWeeny step (an FP64 square and a low-precision product); "
                          "0: FP64 squares X^2, 2X - X^2")
     ap.add_argument("--corr-deriv-tol", type=float, default=None, help="derivative steps stop below this e_k")
+    ap.add_argument("--tail-storage", type=int, default=0,
+                    help="1: the FP64 tail multiplies FP32-stored iterates in FP64 (expansions whose FP64 iterates "
+                         "do not fit in device memory)")
+    ap.add_argument("--low-start-xi", type=float, default=0.0,
+                    help="FP64 squares until the gap image xi_i reaches this value, then --precision")
     ap.add_argument("--no-reference", action="store_true",
                     help="with a low --precision: skip the FP64 reference run (largest workloads)")
     ap.add_argument("--adjoint", action="store_true",
                     help="instead of the expansion benchmark: JVP and VJP of tr(W D) in FP64 and mixed precision")
     ap.add_argument("--adjoint-runs", default="fp64,fp32,bf16x3,bf16x3/fp32",
-                    help="forward[/adjoint] arithmetics of the adjoint benchmark (errors need fp64 first)")
+                    help="forward[/adjoint][@option=value...] arithmetics and options of the adjoint benchmark "
+                         "(errors need fp64 first)")
     ap.add_argument("--switch-tol", type=float, default=None,
                     help="FP64 tail once ||X - X^2||_F < this (default: 0 with the correction, else 1e-3; "
                          "< 0: no FP64 tail)")
@@ -422,12 +477,16 @@ def main():
                     help="instead of the expansion benchmark: the norm comparison (spectral vs Frobenius vs "
                          "Frob-Inf) on banded and permuted matrices of these sizes, e.g. 1024,2048,4096")
     ap.add_argument("--storage", action="store_true",
-                    help="instead of the expansion benchmark: the symmetric square of the converged D against the "
-                         "same product done with a general product's block multiplications")
+                    help="instead of the expansion benchmark: every square of the expansion done in symmetric storage "
+                         "and in general (full-pattern) storage, in --precision (fp64 or bf16x3)")
     ap.add_argument("--n-max-cap", type=int, default=None,
                     help="stop after this many iterations (a capped run of a workload too long for one call)")
     ap.add_argument("--bounds", default=None,
                     help="homo_ub,lumo_lb known in advance (e.g. from a previous SCF cycle): skips the first run")
+    ap.add_argument("--run1-precision", default="fp64", choices=["fp64", "fp32"],
+                    help="arithmetic of the trace-correcting first run (fp32: FP32 squares and an FP64 tail on "
+                         "FP32-stored iterates, for workloads whose FP64 iterates do not fit)")
+    ap.add_argument("--run1-only", action="store_true", help="stop after the trace-correcting first run")
     ap.add_argument("--run1", action="store_true",
                     help="run the trace-correcting first run even when bench_run1.json holds its result")
     args = ap.parse_args()
@@ -466,13 +525,20 @@ def main():
         bounds_from = "run 1 (trace-correcting FP64 run) recorded in bench_run1.json"
     else:
         t = time.perf_counter()
-        r1 = sp2.density(F, no, lmin, lmax, **opts)
+        r1o = dict(opts)
+        if args.run1_precision != "fp64":  # FP32 squares, FP64 tail on FP32-stored iterates
+            r1o.update(precision=args.run1_precision, switch_tol=1e-3, tail_storage=1)
+        r1 = sp2.density(F, no, lmin, lmax, **r1o)
         run1 = {"L": L, "n": info["n"], "tau": tau, "homo_ub": r1.homo_est, "lumo_lb": r1.lumo_est,
-                "n_iter": r1.n_iter, "time_s": round(time.perf_counter() - t, 2)}
+                "n_iter": r1.n_iter, "time_s": round(time.perf_counter() - t, 2), "status": r1.status,
+                "precision": args.run1_precision, "trace_err": abs(trace_of(r1.D) - no)}
         log(f"run 1 (trace-correcting): {json.dumps(run1)}")
         hub, llb = r1.homo_est, r1.lumo_est
-        bounds_from = "run 1 (trace-correcting FP64 run) in this job"
+        bounds_from = f"run 1 (trace-correcting {args.run1_precision.upper()} run) in this job"
         del r1
+        if args.run1_only:
+            print(json.dumps({"run1": run1, "config": args.config}), flush=True)
+            return
 
     if args.calibrate_copy_mib > 0:
         nb = args.calibrate_copy_mib << 20
@@ -484,7 +550,7 @@ def main():
         del src, dst
 
     if args.storage:
-        res = storage_bench(sp2, F, no, lmin, lmax, hub, llb, opts, "fp64" if prec == "bf16x3" else prec)
+        res = storage_bench(sp2, F, no, lmin, lmax, hub, llb, opts, prec if prec != "fp32" else "fp64")
         print(json.dumps({"storage": res, "workload": f"lattice {L}^3 x 4, N={info['n']}, tau={tau}"}), flush=True)
         return
 
@@ -509,6 +575,10 @@ def main():
         mopts["corr_deriv_tol"] = args.corr_deriv_tol
     if args.n_max_cap is not None:
         mopts["n_max_cap"] = args.n_max_cap
+    if args.tail_storage:
+        mopts["tail_storage"] = args.tail_storage
+    if args.low_start_xi > 0.0:
+        mopts["low_start_xi"] = args.low_start_xi
 
     # ---- the timed path, step by step
     recs, res, t_timed = stepped_run(sp2, F, no, lmin, lmax, hub, llb, {**mopts, **opts}, args.warmup, args.steps)

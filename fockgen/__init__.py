@@ -348,3 +348,39 @@ def _zero_padding(n, nbr, bs, I, J, val):
     last = nbr - 1
     val[I == last, bs - pad:, :] = 0.0
     val[J == last, :, bs - pad:] = 0.0
+
+
+# --------------------------------------------------------------------------
+# general (full-pattern) storage: every present block of both triangles
+# --------------------------------------------------------------------------
+
+def random_general_bsr(n, density, seed=0, bs=BS, std=1.0, keep_diag=False):
+    """Random matrix in general block storage (no symmetry): each block of
+    either triangle is present with probability ``density``; entries
+    N(0, std^2); rows and columns past n are zero."""
+    rng = np.random.default_rng(seed)
+    nbr = (n + bs - 1) // bs
+    present = rng.random((nbr, nbr)) < density
+    if keep_diag:
+        present[np.arange(nbr), np.arange(nbr)] = True
+    I, J = np.nonzero(present)  # row-major order: sorted by (I, J)
+    row_ptr = np.zeros(nbr + 1, dtype=np.int64)
+    np.add.at(row_ptr, I + 1, 1)
+    val = rng.normal(0.0, std, size=(I.shape[0], bs, bs))
+    _zero_padding(n, nbr, bs, I, J, val)
+    return BSR(n, np.cumsum(row_ptr), J.astype(np.int32), val, bs)
+
+
+def general_bsr_to_dense(M: BSR):
+    """Dense matrix of a BSR in general storage (blocks as stored)."""
+    bs, nbr = M.bs, M.nbr
+    P = np.zeros((nbr, nbr, bs, bs))
+    P[M.rows(), M.col_idx.astype(np.int64)] = M.val
+    return P.transpose(0, 2, 1, 3).reshape(nbr * bs, nbr * bs)[: M.n, : M.n].copy()
+
+
+def general_block_mask(M: BSR):
+    """nbr x nbr boolean mask of the blocks stored in general storage."""
+    mask = np.zeros((M.nbr, M.nbr), dtype=bool)
+    mask[M.rows(), M.col_idx.astype(np.int64)] = True
+    return mask

@@ -136,6 +136,16 @@ typedef struct {
   int64_t corr_host_mem;   /* pinned host bytes for the copies of X~_i beyond corr_mem (written and read
                               back on a second stream, overlapped with the squares); 0 = 75% of the
                               available host memory, < 0 = none (those iterates are recomputed) */
+  double low_start_xi;     /* mixed precision with homo/lumo bounds: the squares stay in FP64 until the
+                              first X~_i whose gap image xi_i = 1 - q_i - l_i (section "Error control")
+                              reaches this value, then run in the low precision (0 = from X~_0; must be
+                              in [0, 1); ignored by the trace-correcting run) */
+  int32_t tail_storage;    /* storage of the FP64 tail's iterates: 0 = FP64 (default); 1 = FP32, the tail's
+                              squares multiplying the FP32-stored values in FP64 arithmetic (for expansions
+                              whose FP64 iterates do not fit in device memory: the same memory as the FP32
+                              squares, an idempotency floor of about the FP32 rounding of the iterate,
+                              ~2^-24 ||X||_F, instead of the FP32 squares' accumulation noise); not
+                              combined with the correction */
 } sp2_options;
 
 /* Per-run statistics.  Arrays are HOST arrays owned by the caller, each of
@@ -190,7 +200,8 @@ const char *sp2_version(void);
 /* Fill *opt with the defaults: SP2ACC, FP64, switch_tol 1e-3, Frob-Inf,
  * n_max_cap 100, coarse_bs 4096, gamma 1e-3, tau_fixed 0, idem_stop 0,
  * no tape, no subspace correction (corr_purify 2, corr_tol 1e-9, corr_mem 0),
- * adjoint_precision -1. */
+ * adjoint_precision -1, corr_deriv_tol 0, corr_mcweeny 0, corr_host_mem 0, low_start_xi 0,
+ * tail_storage 0. */
 void sp2_options_default(sp2_options *opt);
 
 /* Create a context on HIP device `device` issuing all work on `hip_stream`
@@ -378,6 +389,34 @@ int sp2_square_step(sp2_ctx *ctx, const sp2_bsr *X, double a, double b, double c
  * whole matrix, sums[1] = algorithmic flops (2 * 64^3 per block product). */
 int sp2_pair_product(sp2_ctx *ctx, const sp2_bsr *X, const sp2_bsr *Y, const sp2_bsr *G, int sign, int y_antisym,
                      double a, double b, double c, int precision, sp2_bsr **out, double sums[2]);
+
+/* ---- general (full-pattern) storage ------------------------------------
+ * The format of the paper's general matrix wrapper (section "Implementation
+ * details"), which section "Numerical experiments" compares with the
+ * symmetric one: every present block of both triangles is stored as it is.
+ * Same sp2_bsr struct; within a block row the columns are strictly
+ * increasing, 0 <= col < nbr (any triangle).  No symmetry is assumed. */
+
+/* General storage of the symmetric matrix held by the upper-BSR U: the
+ * stored blocks and, below the diagonal, the transposes of their mirrors.
+ * *G is owned by the caller (sp2_bsr_free). */
+int sp2_general_from_upper(sp2_ctx *ctx, const sp2_bsr *U, sp2_bsr **G);
+
+/* General product out = a I + b G + c A B of matrices in general storage, on
+ * the block pattern of A B (every (I, J) with some K such that A_IK and B_KJ
+ * are stored) joined with the pattern of G and, when a != 0, the diagonal
+ * blocks; the a I term touches only the n real diagonal entries.  G may be
+ * NULL (then b is ignored).  The result is in general storage, owned by the
+ * caller.  sums (may be NULL): sums[0] = ||G - A B||_F^2 (G = 0 when NULL),
+ * sums[1] = tr G, sums[2] = tr(A B), sums[3] = algorithmic flops (2 * 64^3
+ * per block product).  With A = B = G = X (symmetric X in general storage)
+ * this is the square of Algorithm 2 done on both triangles: about twice the
+ * block products and the stored blocks of sp2_square_step.  precision:
+ * SP2_PREC_FP64, or SP2_PREC_BF16X3 (operands rounded to FP32, then split,
+ * FP32 accumulation; the result holds FP32 values); any other value is
+ * SP2_ERR_INVALID_ARG. */
+int sp2_general_product(sp2_ctx *ctx, const sp2_bsr *A, const sp2_bsr *B, const sp2_bsr *G, double a, double b,
+                        double c, int precision, sp2_bsr **out, double sums[4]);
 
 /* Truncation X~ = X + E with ||E|| <= tau in the chosen norm (section "Error
  * control"); diagonal blocks are never removed.  err[0] = ||E||_F,

@@ -26,7 +26,8 @@ EXPORTS = [
     "sp2_last_error", "sp2_gershgorin", "sp2_density", "sp2_vjp", "sp2_jvp", "sp2_replay", "sp2_tape_info",
     "sp2_square_step", "sp2_truncate", "sp2_bsr_copy", "sp2_bsr_free", "sp2_tape_free", "sp2_schedule",
     "sp2_homo_lumo", "sp2_pair_product", "sp2_matrix_norms", "sp2_density_begin", "sp2_density_step",
-    "sp2_density_end", "sp2_solver_free", "sp2_matrix_norms_noalloc",
+    "sp2_density_end", "sp2_solver_free", "sp2_matrix_norms_noalloc", "sp2_general_from_upper",
+    "sp2_general_product",
 ]
 
 
@@ -64,6 +65,8 @@ class sp2_options(C.Structure):
         ("corr_deriv_tol", C.c_double),
         ("corr_mcweeny", C.c_int32),
         ("corr_host_mem", C.c_int64),
+        ("low_start_xi", C.c_double),
+        ("tail_storage", C.c_int32),
     ]
 
 
@@ -189,6 +192,11 @@ def load(path: str = LIB_PATH):
     lib.sp2_pair_product.restype = C.c_int
     lib.sp2_pair_product.argtypes = [C.c_void_p, P(sp2_bsr), P(sp2_bsr), P(sp2_bsr), C.c_int, C.c_int, C.c_double,
                                      C.c_double, C.c_double, C.c_int, P(P(sp2_bsr)), P(C.c_double)]
+    lib.sp2_general_from_upper.restype = C.c_int
+    lib.sp2_general_from_upper.argtypes = [C.c_void_p, P(sp2_bsr), P(P(sp2_bsr))]
+    lib.sp2_general_product.restype = C.c_int
+    lib.sp2_general_product.argtypes = [C.c_void_p, P(sp2_bsr), P(sp2_bsr), P(sp2_bsr), C.c_double, C.c_double,
+                                        C.c_double, C.c_int, P(P(sp2_bsr)), P(C.c_double)]
     lib.sp2_truncate.restype = C.c_int
     lib.sp2_truncate.argtypes = [C.c_void_p, P(sp2_bsr), C.c_double, C.c_int, C.c_int64, P(P(sp2_bsr)),
                                  P(C.c_double)]

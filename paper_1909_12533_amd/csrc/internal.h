@@ -160,9 +160,24 @@ void launch_extract_rows(Ctx &c, const uint32_t *bits, int nbr, int W, const int
                          int32_t *rows);
 // outbits row I (J >= I only) = OR of bits[K] over K in adj row I; with a
 // second (bits2, adj2) set also OR of bits2[K] over K in adj2 row I
+// (upper = false: every column J, for general storage)
 void launch_symbolic(Ctx &c, const uint32_t *bits, const int64_t *adj_ptr, const int32_t *adj_col, int nbr, int W,
                      uint32_t *outbits, const uint32_t *bits2 = nullptr, const int64_t *adj_ptr2 = nullptr,
-                     const int32_t *adj_col2 = nullptr);
+                     const int32_t *adj_col2 = nullptr, bool upper = true);
+// general storage (kernels_general.hip): flag |= 1 for a column outside [0, nbr),
+// 2 for columns not strictly increasing, 4 for a non-monotone row_ptr
+void launch_validate_general(Ctx &c, const int64_t *row_ptr, const int32_t *col_idx, int nbr, int64_t nnzb,
+                             int32_t *flag);
+// block map and bitmaps of a general pattern: idxmap[R nbr + C] = slot and bit C
+// of bits row R, with (R, C) = (I, J), or (J, I) for transpose; idxmap may be null
+void launch_build_maps_general(Ctx &c, const int32_t *row_of, const int32_t *col_idx, const int32_t *slot,
+                               int64_t nnzb, int nbr, int W, bool transpose, int32_t *idxmap, uint32_t *bits);
+// out |= g (if not null), and the diagonal bits with diag
+void launch_or_general(Ctx &c, uint32_t *out, const uint32_t *g, int nbr, int W, bool diag);
+// general storage of a symmetric upper-BSR matrix: output block (I, J) (pattern
+// row_of / col) is the stored block idxmap[I nbr + J] of src, transposed for I > J
+void launch_expand_upper(Ctx &c, const int32_t *row_of, const int32_t *col, int64_t nout, int nbr,
+                         const int32_t *idxmap, const double *src, double *dst);
 // out = upper part (J >= I) of a | b (symmetric block-row bitmaps)
 void launch_or_upper(Ctx &c, const uint32_t *a, const uint32_t *b, int nbr, int W, uint32_t *out);
 // out (FP64, by output position) = a A + b B over an output pattern given by (row_of, col)
@@ -229,6 +244,8 @@ struct TileArgs {
   const int32_t *oidx;     // nbr x nbr: pattern position of output block (I, J), or -1
   const int32_t *tiles;    // ntiles pairs (TI, TJ), TI <= TJ in units of tb blocks
   int tb = 2;              // tile edge in blocks: 2 (every kernel) or 4 (BF16x3, dense patterns)
+  int full = 0;            // general storage: X (direct map, row bitmaps) times Y (map and bitmaps of Y^T),
+                           // every block stored as is (no transposed reads), output tiles of both triangles
   int64_t ntiles;
   int64_t xcd_chunk;       // tiles per XCD: workgroup b runs tile (b % 8) * xcd_chunk + b / 8
   void *opool;             // output block at its pattern position
@@ -237,7 +254,9 @@ struct TileArgs {
   int64_t n;
   double *parts;           // by pattern position, NPART each
 };
-int64_t build_tiles(Ctx &c, const int32_t *oidx, int nbr, Buf &tiles, int tb = 2);
+// output tiles holding at least one output block: TI <= TJ (upper output), or
+// every tile with full = true (general storage)
+int64_t build_tiles(Ctx &c, const int32_t *oidx, int nbr, Buf &tiles, int tb = 2, bool full = false);
 void launch_square_tile(Ctx &c, int mode, const TileArgs &a);
 // FP64 squares and products with operands loaded straight to LDS (kernels_f64.hip)
 void launch_square_f64_lds(Ctx &c, const TileArgs &a);

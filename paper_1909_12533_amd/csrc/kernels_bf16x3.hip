@@ -69,7 +69,9 @@ __global__ __launch_bounds__(TPB) void k_pack_bf16x3(const float *pool, const in
   }
 }
 
-template <typename TO, bool GEN>
+// FULL (with GEN, one pass): general storage, A = X_{I,K} always image N of
+// its stored block, B = Y_{K,J} always image T; output blocks of both triangles
+template <typename TO, bool GEN, bool FULL = false>
 __global__ __launch_bounds__(TPB, 2) void k_square_tile_bf16x3(TileArgs a) {
   // operand o (A0, A1, B0, B1) x plane (hi, lo)
   __shared__ __align__(16) uint16_t L[4][2][PLANE];
@@ -83,7 +85,7 @@ __global__ __launch_bounds__(TPB, 2) void k_square_tile_bf16x3(TileArgs a) {
   const int I = I0 + ia, J = J0 + jb;
   const bool has_i1 = I0 + 1 < nbr, has_j1 = J0 + 1 < nbr;
   int32_t pos = -1;
-  if (I < nbr && J < nbr && I <= J) pos = __builtin_amdgcn_readfirstlane(a.oidx[(int64_t)I * nbr + J]);
+  if (I < nbr && J < nbr && (FULL || I <= J)) pos = __builtin_amdgcn_readfirstlane(a.oidx[(int64_t)I * nbr + J]);
   const u32x4 *xq = static_cast<const u32x4 *>(a.xpack);
   const u32x4 *yq = static_cast<const u32x4 *>(GEN ? a.ypack : a.xpack);
 
@@ -152,7 +154,8 @@ __global__ __launch_bounds__(TPB, 2) void k_square_tile_bf16x3(TileArgs a) {
     s1 = has_i1 ? __builtin_amdgcn_readfirstlane(li_[(int64_t)(I0 + 1) * nbr + (KK)]) : -1;   \
     s2 = __builtin_amdgcn_readfirstlane(ri_[(int64_t)J0 * nbr + (KK)]);                      \
     s3 = has_j1 ? __builtin_amdgcn_readfirstlane(ri_[(int64_t)(J0 + 1) * nbr + (KK)]) : -1;  \
-    const bool n0_ = I0 <= (KK), n1_ = I0 + 1 <= (KK), n2_ = (KK) > J0, n3_ = (KK) > J0 + 1; \
+    const bool n0_ = FULL || I0 <= (KK), n1_ = FULL || I0 + 1 <= (KK);                       \
+    const bool n2_ = !FULL && (KK) > J0, n3_ = !FULL && (KK) > J0 + 1;                       \
     if (GEN) {                                                                               \
       const bool la_ = (KP) ? a.yanti : a.xanti, ra_ = (KP) ? a.xanti : a.yanti;             \
       const bool ng_ = (KP) && a.neg2;                                                       \
@@ -265,7 +268,7 @@ struct Stage4 {
   uint32_t ga, gb0, gb1;
 };
 
-template <typename TO, bool GEN>
+template <typename TO, bool GEN, bool FULL = false>
 __global__ __launch_bounds__(512, 2) void k_square_tile4_bf16x3(TileArgs a) {
   __shared__ __align__(16) uint16_t S0[8][2][HPLANE];  // k half 0 of the current K
   __shared__ __align__(16) uint16_t S1[8][2][HPLANE];  // k half 1
@@ -279,8 +282,10 @@ __global__ __launch_bounds__(512, 2) void k_square_tile4_bf16x3(TileArgs a) {
   const int ia = wave >> 1, jp = 2 * (wave & 1);
   const int I = I0 + ia, Jb0 = J0 + jp, Jb1 = J0 + jp + 1;
   int32_t pos0 = -1, pos1 = -1;
-  if (I < nbr && Jb0 < nbr && I <= Jb0) pos0 = __builtin_amdgcn_readfirstlane(a.oidx[(int64_t)I * nbr + Jb0]);
-  if (I < nbr && Jb1 < nbr && I <= Jb1) pos1 = __builtin_amdgcn_readfirstlane(a.oidx[(int64_t)I * nbr + Jb1]);
+  if (I < nbr && Jb0 < nbr && (FULL || I <= Jb0))
+    pos0 = __builtin_amdgcn_readfirstlane(a.oidx[(int64_t)I * nbr + Jb0]);
+  if (I < nbr && Jb1 < nbr && (FULL || I <= Jb1))
+    pos1 = __builtin_amdgcn_readfirstlane(a.oidx[(int64_t)I * nbr + Jb1]);
   const u32x4 *xq = static_cast<const u32x4 *>(a.xpack);
   const u32x4 *yq = static_cast<const u32x4 *>(GEN ? a.ypack : a.xpack);
 
@@ -350,7 +355,7 @@ __global__ __launch_bounds__(512, 2) void k_square_tile4_bf16x3(TileArgs a) {
   auto dma = [&](const Stage4 &q, int kh, uint16_t (*st)[2][HPLANE]) {
     const u32x4 *base = ((wave < 4) == !(GEN && q.kp)) ? xq : yq;
     const int32_t so = q.sd > 0 ? q.sd : 0;  // absent: slot 0, never multiplied
-    const bool nimg = wave < 4 ? (I0 + wave <= q.K) : (q.K > J0 + wave - 4);
+    const bool nimg = wave < 4 ? (FULL || I0 + wave <= q.K) : (!FULL && q.K > J0 + wave - 4);
     const char *img =
         reinterpret_cast<const char *>(base + (int64_t)so * BLK_Q + (nimg ? 0 : IMG_Q) + kh * 4);
 #pragma unroll
@@ -460,6 +465,16 @@ void launch_square_tile_bf16x3(Ctx &c, const TileArgs &a) {
   const bool gen = a.ypool != a.xpool || a.npass != 1 || a.xanti || a.yanti;
   if (!a.xpack || (gen && !a.ypack)) fail(SP2_ERR_INVALID_ARG, "BF16x3 square needs packed operands");
   const unsigned g = (unsigned)(8 * a.xcd_chunk);
+  if (a.full) {
+    if (!a.ypack || a.npass != 1 || a.xanti || a.yanti || a.oprec != P32)
+      fail(SP2_ERR_INVALID_ARG, "general-storage BF16x3 product: one pass, FP32 output, both operands");
+    if (a.tb == 4)
+      k_square_tile4_bf16x3<float, true, true><<<g, 512, 0, c.stream>>>(a);
+    else
+      k_square_tile_bf16x3<float, true, true><<<g, TPB, 0, c.stream>>>(a);
+    SP2_LAUNCH_CHECK();
+    return;
+  }
   if (a.tb == 4) {
     if (a.oprec == P32) {
       if (gen)

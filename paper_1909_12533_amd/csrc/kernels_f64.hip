@@ -100,7 +100,10 @@ __device__ __forceinline__ void mma_quarter(d4 (&acc)[4][4], const char *st, int
 
 // GEN: general product (second operand Y, a second pass with the roles
 // swapped and its sign, antisymmetric operands); otherwise the square X X.
-template <typename TO, bool GEN>
+// FULL (with GEN, one pass): general storage, X and Y blocks read as stored
+// (X by its direct map, Y by the map of its transpose), output blocks of both
+// triangles.
+template <typename TO, bool GEN, bool FULL = false>
 __global__ __launch_bounds__(256, 2) void k_square_f64_lds(TileArgs a) {
   __shared__ __align__(16) double S0[4][QS];  // even quarters: A0, A1, B0, B1
   __shared__ __align__(16) double S1[4][QS];  // odd quarters
@@ -115,7 +118,7 @@ __global__ __launch_bounds__(256, 2) void k_square_f64_lds(TileArgs a) {
   const int I = I0 + ia, J = J0 + jb;
   const bool has_i1 = I0 + 1 < nbr, has_j1 = J0 + 1 < nbr;
   int32_t pos = -1;
-  if (I < nbr && J < nbr && I <= J) pos = __builtin_amdgcn_readfirstlane(a.oidx[(int64_t)I * nbr + J]);
+  if (I < nbr && J < nbr && (FULL || I <= J)) pos = __builtin_amdgcn_readfirstlane(a.oidx[(int64_t)I * nbr + J]);
 
   d4 acc[4][4];
 #pragma unroll
@@ -179,12 +182,12 @@ __global__ __launch_bounds__(256, 2) void k_square_f64_lds(TileArgs a) {
     const int32_t *ri = (GEN ? (kp ? a.idxmap : a.yidxmap) : a.idxmap) + vz;
     q.sa = li[(int64_t)(I < nbr ? I : 0) * nbr + K];
     q.sb = ri[(int64_t)(J < nbr ? J : 0) * nbr + K];
-    q.ka = !(I > K);
-    q.kb = K > J;
+    q.ka = FULL || !(I > K);
+    q.kb = !FULL && K > J;
     q.sd = (wave < 2 ? li : ri)[(int64_t)(Rd < nbr ? Rd : 0) * nbr + K];
-    q.kd = wave < 2 ? !(Rd > K) : (K > Rd);
+    q.kd = wave < 2 ? (FULL || !(Rd > K)) : (!FULL && K > Rd);
     q.kp = kp;
-    if (GEN) {
+    if (GEN && !FULL) {
       const bool la = kp ? a.yanti : a.xanti, ra = kp ? a.xanti : a.yanti;
       q.na = (la && I > K) != (kp && a.neg2);
       q.nb = ra && K > J;
@@ -291,7 +294,11 @@ void launch_square_f64_lds(Ctx &c, const TileArgs &a) {
   if (gen && !(a.ypool && a.yidxmap && a.ybits && (a.npass == 1 || a.npass == 2)))
     fail(SP2_ERR_INVALID_ARG, "tiled product: incomplete second operand");
   const unsigned g = (unsigned)(8 * a.xcd_chunk);
-  if (a.oprec == P32) {  // FP64 arithmetic, result rounded to FP32 (the correction's commutator)
+  if (a.full) {
+    if (!(a.ypool && a.yidxmap && a.ybits) || a.npass != 1 || a.xanti || a.yanti || a.oprec != P64)
+      fail(SP2_ERR_INVALID_ARG, "general-storage product: one pass, FP64 output, both operands");
+    k_square_f64_lds<double, true, true><<<g, 256, 0, c.stream>>>(a);
+  } else if (a.oprec == P32) {  // FP64 arithmetic, result rounded to FP32 (the correction's commutator)
     if (!gen) fail(SP2_ERR_INVALID_ARG, "FP64 square with FP32 output is for products only");
     k_square_f64_lds<float, true><<<g, 256, 0, c.stream>>>(a);
   } else if (gen) {

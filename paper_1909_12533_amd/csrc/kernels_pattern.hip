@@ -121,10 +121,11 @@ __global__ void k_extract_rows(const uint32_t *bits, int nbr, int W, const int64
   }
 }
 
-// outbits[I] = OR over K in adj(I) of bits[K], restricted to columns J >= I.
+// outbits[I] = OR over K in adj(I) of bits[K], restricted to columns J >= I
+// when upper (symmetric storage), every column otherwise (general storage).
 __global__ void k_symbolic(const uint32_t *bits, const int64_t *adj_ptr, const int32_t *adj_col, int nbr, int W,
                            int WP, uint32_t *outbits, const uint32_t *bits2, const int64_t *adj_ptr2,
-                           const int32_t *adj_col2) {
+                           const int32_t *adj_col2, bool upper) {
   __shared__ uint32_t sh[TPB];
   const int I = blockIdx.x;
   if (I >= nbr) return;
@@ -144,10 +145,12 @@ __global__ void k_symbolic(const uint32_t *bits, const int64_t *adj_ptr, const i
     if (g == 0 && w < W) {
       for (int gg = 1; gg < G; ++gg) acc |= sh[gg * WP + wl];
       const int lo = w * 32;
-      if (lo + 32 <= I)
-        acc = 0;
-      else if (lo < I)
-        acc &= ~((1u << (I - lo)) - 1u);
+      if (upper) {
+        if (lo + 32 <= I)
+          acc = 0;
+        else if (lo < I)
+          acc &= ~((1u << (I - lo)) - 1u);
+      }
       outbits[(int64_t)I * W + w] = acc;
     }
     __syncthreads();
@@ -316,12 +319,14 @@ void launch_extract_rows(Ctx &c, const uint32_t *bits, int nbr, int W, const int
   SP2_LAUNCH_CHECK();
 }
 void launch_symbolic(Ctx &c, const uint32_t *bits, const int64_t *adj_ptr, const int32_t *adj_col, int nbr, int W,
-                     uint32_t *outbits, const uint32_t *bits2, const int64_t *adj_ptr2, const int32_t *adj_col2) {
+                     uint32_t *outbits, const uint32_t *bits2, const int64_t *adj_ptr2, const int32_t *adj_col2,
+                     bool upper) {
   if (nbr <= 0) return;
   if (bits2 && !(adj_ptr2 && adj_col2)) fail(SP2_ERR_INVALID_ARG, "symbolic product: incomplete second operand");
   int WP = 1;
   while (WP < W && WP < TPB) WP <<= 1;
-  k_symbolic<<<nbr, TPB, 0, c.stream>>>(bits, adj_ptr, adj_col, nbr, W, WP, outbits, bits2, adj_ptr2, adj_col2);
+  k_symbolic<<<nbr, TPB, 0, c.stream>>>(bits, adj_ptr, adj_col, nbr, W, WP, outbits, bits2, adj_ptr2, adj_col2,
+                                        upper);
   SP2_LAUNCH_CHECK();
 }
 

@@ -93,8 +93,12 @@ __device__ inline void mma_dispatch(typename MF<T>::acc_t (&acc)[MT][4], const T
 // NW = 4: one wave per output block (all 4 x 4 MFMA tiles); NW = 8: two waves
 // per output block, each with the 2 x 4 tiles of rows 32 h .. 32 h + 31, so
 // that every SIMD holds two waves (one multiplies while the other waits on LDS).
-template <typename T, typename TO, bool GEN, int NW>
+// TI: element type of the stored operands (and of G); T = double with
+// TI = float multiplies FP32-stored values in FP64 (each value widened
+// exactly when it is written to LDS).
+template <typename T, typename TO, bool GEN, int NW, typename TI = T>
 __global__ __launch_bounds__(64 * NW, (NW == 4 && sizeof(T) == 4) ? 2 : 1) void k_square_tile(TileArgs a) {
+  static_assert(sizeof(TI) <= sizeof(T), "operands are widened, never narrowed");
   constexpr int LD = MF<T>::LD;
   constexpr int NT = 64 * NW;      // threads
   constexpr int MT = 16 / NW;      // 16-row A tiles per wave
@@ -154,8 +158,9 @@ __global__ __launch_bounds__(64 * NW, (NW == 4 && sizeof(T) == 4) ? 2 : 1) void 
 
   // staged operand blocks A0 = L_{I0,K}, A1 = L_{I0+1,K}, B0 = R_{K,J0}, B1 = R_{K,J0+1}
   // with (L, R) = (X, Y) in the first pass and (Y, X) in the second
-  constexpr int NCH = BB / Stage<T>::EPC / NT;  // 16-byte chunks per thread and block
-  constexpr int QB = BB * (int)sizeof(T) / 16;  // 16-byte chunks per block
+  constexpr int EPC = Stage<TI>::EPC;            // stored elements per 16-byte chunk
+  constexpr int NCH = BB / EPC / NT;             // 16-byte chunks per thread and block
+  constexpr int QB = BB * (int)sizeof(TI) / 16;  // 16-byte chunks per block
   constexpr uint32_t SGN = 0x80000000u;
   const u32x4 *xq = reinterpret_cast<const u32x4 *>(a.xpool);
   const u32x4 *yq = reinterpret_cast<const u32x4 *>(GEN ? a.ypool : a.xpool);
@@ -201,7 +206,22 @@ __global__ __launch_bounds__(64 * NW, (NW == 4 && sizeof(T) == 4) ? 2 : 1) void 
   while (K >= 0) {
     const int32_t c0 = s0, c1 = s1, c2 = s2, c3 = s3;
     __syncthreads();  // previous tiles fully consumed
-    if (GEN) {
+    if constexpr (sizeof(TI) < sizeof(T)) {
+      // FP32-stored values, FP64 arithmetic: 4 floats per chunk, widened
+      // (exactly) to 4 doubles, sign flips applied to the floats first
+#pragma unroll
+      for (int j = 0; j < NCH; ++j) {
+        const int e = (j * NT + (int)threadIdx.x) * EPC;
+        const int o = (e >> 6) * LD + (e & 63);
+        const u32x4 w[4] = {r0[j] ^ u32x4{g0, g0, g0, g0}, r1[j] ^ u32x4{g1, g1, g1, g1},
+                            r2[j] ^ u32x4{g2, g2, g2, g2}, r3[j] ^ u32x4{g3, g3, g3, g3}};
+        T *dst[4] = {&As[0][o], &As[1][o], &Bs[0][o], &Bs[1][o]};
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) dst[b][v] = (T)__uint_as_float(w[b][v]);
+      }
+    } else if (GEN) {
       // sign flips on the staged words (FP64: the high word of each double)
       const uint32_t lo0 = sizeof(T) == 8 ? 0u : g0, lo1 = sizeof(T) == 8 ? 0u : g1;
       const uint32_t lo2 = sizeof(T) == 8 ? 0u : g2, lo3 = sizeof(T) == 8 ? 0u : g3;
@@ -209,7 +229,7 @@ __global__ __launch_bounds__(64 * NW, (NW == 4 && sizeof(T) == 4) ? 2 : 1) void 
       const u32x4 m2 = u32x4{lo2, g2, lo2, g2}, m3 = u32x4{lo3, g3, lo3, g3};
 #pragma unroll
       for (int j = 0; j < NCH; ++j) {
-        const int e = (j * NT + (int)threadIdx.x) * Stage<T>::EPC;
+        const int e = (j * NT + (int)threadIdx.x) * EPC;
         const int o = (e >> 6) * LD + (e & 63);
         *reinterpret_cast<u32x4 *>(&As[0][o]) = r0[j] ^ m0;
         *reinterpret_cast<u32x4 *>(&As[1][o]) = r1[j] ^ m1;
@@ -219,7 +239,7 @@ __global__ __launch_bounds__(64 * NW, (NW == 4 && sizeof(T) == 4) ? 2 : 1) void 
     } else {
 #pragma unroll
       for (int j = 0; j < NCH; ++j) {
-        const int e = (j * NT + (int)threadIdx.x) * Stage<T>::EPC;
+        const int e = (j * NT + (int)threadIdx.x) * EPC;
         const int o = (e >> 6) * LD + (e & 63);
         *reinterpret_cast<u32x4 *>(&As[0][o]) = r0[j];
         *reinterpret_cast<u32x4 *>(&As[1][o]) = r1[j];
@@ -242,12 +262,12 @@ __global__ __launch_bounds__(64 * NW, (NW == 4 && sizeof(T) == 4) ? 2 : 1) void 
   const auto rowf = [](int g, int q) { return MF<T>::row(g, q); };
   if constexpr (NW == 4) {
     if (pos < 0) return;
-    square_epilogue<T, TO>(acc, a, I, J, pos, nk, rowf);
+    square_epilogue<TI, TO>(acc, a, I, J, pos, nk, rowf);
   } else {
   // two waves per block: the second half's partial sums are added (in a fixed
   // order) by the first half's wave
   EpiSums ps{};
-  if (pos >= 0) ps = epilogue_rows<T, TO, MT>(acc, a, I, J, pos, row0, rowf);
+  if (pos >= 0) ps = epilogue_rows<TI, TO, MT>(acc, a, I, J, pos, row0, rowf);
   const int lane = threadIdx.x & 63;
   if (half == 1 && lane == 0) {
     red[blk][0] = ps.e2;
@@ -273,7 +293,7 @@ __global__ __launch_bounds__(64 * NW, (NW == 4 && sizeof(T) == 4) ? 2 : 1) void 
 // TJ = STJ * ST + tj.
 constexpr int ST = 4;
 
-__device__ inline bool tile_of(int64_t id, int ntr, int nst, int &TI, int &TJ) {
+__device__ inline bool tile_of(int64_t id, int ntr, int nst, bool full, int &TI, int &TJ) {
   const int tj = (int)(id % ST);
   const int64_t r1 = id / ST;
   const int ti = (int)(r1 % ST);
@@ -281,30 +301,32 @@ __device__ inline bool tile_of(int64_t id, int ntr, int nst, int &TI, int &TJ) {
   const int STJ = (int)(r2 % nst), STI = (int)(r2 / nst);
   TI = STI * ST + ti;
   TJ = STJ * ST + tj;
-  return TI < ntr && TJ < ntr && TI <= TJ;
+  return TI < ntr && TJ < ntr && (full || TI <= TJ);
 }
 
 // flags of tb x tb output tiles holding at least one output block
-__global__ void k_tile_flags(const int32_t *oidx, int nbr, int tb, int ntr, int nst, int64_t nid, int64_t *flag) {
+__global__ void k_tile_flags(const int32_t *oidx, int nbr, int tb, int ntr, int nst, int64_t nid, bool full,
+                             int64_t *flag) {
   const int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (id >= nid) return;
   int TI, TJ;
   int64_t f = 0;
-  if (tile_of(id, ntr, nst, TI, TJ)) {
+  if (tile_of(id, ntr, nst, full, TI, TJ)) {
     for (int a = 0; a < tb; ++a)
       for (int b = 0; b < tb; ++b) {
         const int I = tb * TI + a, J = tb * TJ + b;
-        if (I < nbr && J < nbr && I <= J && oidx[(int64_t)I * nbr + J] >= 0) f = 1;
+        if (I < nbr && J < nbr && (full || I <= J) && oidx[(int64_t)I * nbr + J] >= 0) f = 1;
       }
   }
   flag[id] = f;
 }
 
-__global__ void k_tile_write(const int64_t *flag, const int64_t *pos, int ntr, int nst, int64_t nid, int32_t *tiles) {
+__global__ void k_tile_write(const int64_t *flag, const int64_t *pos, int ntr, int nst, int64_t nid, bool full,
+                             int32_t *tiles) {
   const int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (id >= nid || !flag[id]) return;
   int TI, TJ;
-  tile_of(id, ntr, nst, TI, TJ);
+  tile_of(id, ntr, nst, full, TI, TJ);
   const int64_t o = pos[id];
   tiles[2 * o] = TI;
   tiles[2 * o + 1] = TJ;
@@ -312,13 +334,13 @@ __global__ void k_tile_write(const int64_t *flag, const int64_t *pos, int ntr, i
 
 }  // namespace
 
-int64_t build_tiles(Ctx &c, const int32_t *oidx, int nbr, Buf &tiles, int tb) {
+int64_t build_tiles(Ctx &c, const int32_t *oidx, int nbr, Buf &tiles, int tb, bool full) {
   if (tb != 2 && tb != 4) fail(SP2_ERR_INVALID_ARG, "tile edge must be 2 or 4 blocks");
   const int ntr = (nbr + tb - 1) / tb;
   const int nst = (ntr + ST - 1) / ST;
   const int64_t nid = (int64_t)nst * nst * ST * ST;
   Buf flag = c.alloc(sizeof(int64_t) * nid), pos = c.alloc(sizeof(int64_t) * (nid + 1));
-  k_tile_flags<<<(unsigned)((nid + TPB - 1) / TPB), TPB, 0, c.stream>>>(oidx, nbr, tb, ntr, nst, nid,
+  k_tile_flags<<<(unsigned)((nid + TPB - 1) / TPB), TPB, 0, c.stream>>>(oidx, nbr, tb, ntr, nst, nid, full,
                                                                         flag.as<int64_t>());
   SP2_LAUNCH_CHECK();
   scan_exclusive_i64(c, flag.as<int64_t>(), pos.as<int64_t>(), nid);
@@ -326,20 +348,25 @@ int64_t build_tiles(Ctx &c, const int32_t *oidx, int nbr, Buf &tiles, int tb) {
   c.d2h(&nt, pos.as<int64_t>() + nid, sizeof(int64_t));
   tiles = c.alloc(sizeof(int32_t) * 2 * (nt > 0 ? nt : 1));
   k_tile_write<<<(unsigned)((nid + TPB - 1) / TPB), TPB, 0, c.stream>>>(flag.as<int64_t>(), pos.as<int64_t>(), ntr, nst,
-                                                                        nid, tiles.as<int32_t>());
+                                                                        nid, full, tiles.as<int32_t>());
   SP2_LAUNCH_CHECK();
   return nt;
 }
 
 void launch_square_tile(Ctx &c, int mode, const TileArgs &a) {
   if (a.ntiles <= 0) return;
+  if (a.full) fail(SP2_ERR_INVALID_ARG, "register-staged tiled kernel: symmetric storage only");
   if (a.tb != 2 && mode != M_BF16X3) fail(SP2_ERR_INVALID_ARG, "4 x 4 tiles are for the BF16x3 square only");
   const bool gen = a.ypool != a.xpool || a.npass != 1 || a.xanti || a.yanti;
   if (gen && !(a.ypool && a.yidxmap && a.ybits && (a.npass == 1 || a.npass == 2)))
     fail(SP2_ERR_INVALID_ARG, "tiled product: incomplete second operand");
   const unsigned g = (unsigned)(8 * a.xcd_chunk);
-  if (mode == M_F64) {
-    if (a.xprec != P64) fail(SP2_ERR_INVALID_ARG, "FP64 square needs FP64 input pools");
+  if (mode == M_F64 && a.xprec == P32) {
+    // FP64 arithmetic on FP32-stored values, FP32 result (the FP64 tail of an
+    // expansion whose FP64 iterates do not fit in device memory)
+    if (gen || a.oprec != P32) fail(SP2_ERR_INVALID_ARG, "FP64 square of FP32 values: square only, FP32 result");
+    k_square_tile<double, float, false, 8, float><<<g, 512, 0, c.stream>>>(a);
+  } else if (mode == M_F64) {
     if (a.oprec == P32) {  // FP64 arithmetic, result rounded to FP32 (the correction's commutator)
       if (!gen) fail(SP2_ERR_INVALID_ARG, "FP64 square with FP32 output is for products only");
       k_square_tile<double, float, true, 8><<<g, 512, 0, c.stream>>>(a);

@@ -66,7 +66,8 @@ __device__ inline double wave_sum(double v) {
 // Epilogue for the rows r0 + 16 m + rowf(g, v) (m < MT) of the 64 x 64 output
 // block (I, J), held by one wave in MT x 4 MFMA 16 x 16 accumulator tiles S:
 // out = ca I + cb G + cc S is written at pattern position pos, and the
-// wave's partial sums (||G - S||^2 weighted by 2 off the diagonal, tr G, tr S,
+// wave's partial sums (||G - S||^2 weighted by 2 off the diagonal unless the
+// storage is general, tr G, tr S,
 // ||out||^2) are returned, reduced over the wave.  In the square G = X, so
 // these are e^2, tr X~ and tr X~^2.
 struct EpiSums {
@@ -107,7 +108,7 @@ __device__ inline EpiSums epilogue_rows(const ACC (&acc)[MT][4], const TileArgs 
         }
       }
   EpiSums ps;
-  ps.e2 = wave_sum((I == J) ? e2 : 2.0 * e2);
+  ps.e2 = wave_sum((I == J || a.full) ? e2 : 2.0 * e2);
   ps.tx = wave_sum(tx);
   ps.ts = wave_sum(ts);
   ps.nr = wave_sum(nr);

@@ -70,7 +70,9 @@ void check_input(const sp2_bsr *M, const char *what) {
 
 // Borrowed upper BSR -> internal pattern (row_of computed, slot = identity).
 // Validates the structure on the device.
-Pattern borrow_pattern(Ctx &c, const sp2_bsr *M, const char *what) {
+// general: the matrix is in general storage (any column 0 <= col < nbr);
+// otherwise symmetric upper storage (row <= col)
+Pattern borrow_pattern(Ctx &c, const sp2_bsr *M, const char *what, bool general = false) {
   check_input(M, what);
   Pattern p;
   p.n = M->n;
@@ -87,10 +89,15 @@ Pattern borrow_pattern(Ctx &c, const sp2_bsr *M, const char *what) {
   launch_row_of(c, M->row_ptr, p.nbr, p.row_of.as<int32_t>());
   Buf flag = c.alloc(sizeof(int32_t));
   launch_fill_i32(c, flag.as<int32_t>(), 1, 0);
-  launch_validate_pattern(c, M->row_ptr, M->col_idx, p.nbr, p.nnzb, flag.as<int32_t>());
+  if (general)
+    launch_validate_general(c, M->row_ptr, M->col_idx, p.nbr, p.nnzb, flag.as<int32_t>());
+  else
+    launch_validate_pattern(c, M->row_ptr, M->col_idx, p.nbr, p.nnzb, flag.as<int32_t>());
   int32_t f = 0;
   c.d2h(&f, flag.p, sizeof(f));
-  if (f) fail(SP2_ERR_INVALID_ARG, std::string(what) + ": columns must satisfy row <= col < nbr, strictly increasing");
+  if (f)
+    fail(SP2_ERR_INVALID_ARG, std::string(what) + (general ? ": columns must satisfy 0 <= col < nbr, strictly increasing"
+                                                           : ": columns must satisfy row <= col < nbr, strictly increasing"));
   return p;
 }
 
@@ -226,9 +233,9 @@ sp2_bsr *export_bsr(Ctx &c, const DMat &m) {
 }
 
 // borrowed input matrix as an internal DMat (values not copied)
-DMat borrow_matrix(Ctx &c, const sp2_bsr *M, const char *what) {
+DMat borrow_matrix(Ctx &c, const sp2_bsr *M, const char *what, bool general = false) {
   DMat d;
-  d.pat = borrow_pattern(c, M, what);
+  d.pat = borrow_pattern(c, M, what, general);
   d.pool = std::make_shared<Pool>();
   d.pool->prec = P64;
   d.pool->nslots = M->nnzb;
@@ -461,6 +468,130 @@ DMat add_union(Ctx &c, const DMat &A, double a, const DMat &Bm, double b) {
   launch_add_union(c, o.pat.row_of.as<int32_t>(), o.pat.col_idx.as<int32_t>(), o.pat.nnzb, ma.nbr, A.pool->vals.p,
                    A.pool->prec, ma.idxmap.as<int32_t>(), a, Bm.pool->vals.p, Bm.pool->prec,
                    mb.idxmap.as<int32_t>(), b, o.pool->vals.as<double>());
+  return o;
+}
+
+// ------------------------------------------------------- general storage
+// Block map and bitmaps of a general pattern (of its transpose with
+// transpose), adjacency lists of the bitmap rows with with_adj.
+Maps build_maps_general(Ctx &c, const Pattern &p, bool transpose, bool with_idx, bool with_adj) {
+  Maps m;
+  m.nbr = p.nbr;
+  m.W = (p.nbr + 31) / 32;
+  if (with_idx) m.idxmap = c.alloc(sizeof(int32_t) * (size_t)p.nbr * p.nbr);
+  m.bits = c.alloc(sizeof(uint32_t) * (size_t)p.nbr * m.W);
+  launch_build_maps_general(c, p.row_of.as<int32_t>(), p.col_idx.as<int32_t>(), slot_ptr(p), p.nnzb, p.nbr, m.W,
+                            transpose, with_idx ? m.idxmap.as<int32_t>() : nullptr, m.bits.as<uint32_t>());
+  if (with_adj) {
+    Buf cnt = c.alloc(sizeof(int64_t) * p.nbr);
+    m.adj_ptr = c.alloc(sizeof(int64_t) * (p.nbr + 1));
+    launch_popcount_rows(c, m.bits.as<uint32_t>(), p.nbr, m.W, cnt.as<int64_t>());
+    scan_exclusive_i64(c, cnt.as<int64_t>(), m.adj_ptr.as<int64_t>(), p.nbr);
+    c.d2h(&m.nadj, m.adj_ptr.as<int64_t>() + p.nbr, sizeof(int64_t));
+    m.adj_col = c.alloc(sizeof(int32_t) * (m.nadj > 0 ? m.nadj : 1));
+    launch_extract_rows(c, m.bits.as<uint32_t>(), p.nbr, m.W, m.adj_ptr.as<int64_t>(), m.adj_col.as<int32_t>(),
+                        nullptr);
+  }
+  return m;
+}
+
+// out = ca I + cb G + cc A B for A, B (and G) in general storage, on the block
+// pattern of A B joined with G's and, when ca != 0, the diagonal; output in
+// general storage.  mode M_F64 (FP64 operands) or M_BF16X3 (FP32 operands).
+SquareOut general_product(Ctx &c, const DMat &A, const DMat &Bm, const DMat *G, double ca, double cb, double cc,
+                          int mode) {
+  const auto t0 = std::chrono::steady_clock::now();
+  const int need = mode == M_F64 ? P64 : P32;
+  if (mode != M_F64 && mode != M_BF16X3) fail(SP2_ERR_INVALID_ARG, "general product: FP64 or BF16x3 arithmetic");
+  if (A.pool->prec != need || Bm.pool->prec != need || (G && G->pool->prec != need))
+    fail(SP2_ERR_INVALID_ARG, "general product: operand precision does not match the arithmetic");
+  if (A.pat.nbr != Bm.pat.nbr || A.pat.n != Bm.pat.n || (G && G->pat.n != A.pat.n))
+    fail(SP2_ERR_INVALID_ARG, "general product: operand sizes differ");
+  const int nbr = A.pat.nbr;
+  Maps ma = build_maps_general(c, A.pat, false, true, true);   // rows I of A: K lists, slots
+  Maps mbr = build_maps_general(c, Bm.pat, false, false, false);  // rows K of B (symbolic)
+  Maps mbt = build_maps_general(c, Bm.pat, true, true, false);   // columns J of B: K bits, slots
+  Maps mg;
+  if (G) mg = build_maps_general(c, G->pat, false, true, false);
+  SquareOut r;
+  {
+    Buf outbits = c.alloc(sizeof(uint32_t) * (size_t)nbr * ma.W);
+    launch_symbolic(c, mbr.bits.as<uint32_t>(), ma.adj_ptr.as<int64_t>(), ma.adj_col.as<int32_t>(), nbr, ma.W,
+                    outbits.as<uint32_t>(), nullptr, nullptr, nullptr, false);
+    launch_or_general(c, outbits.as<uint32_t>(), G ? mg.bits.as<uint32_t>() : nullptr, nbr, ma.W, ca != 0.0);
+    r.next.pat = pattern_from_bits(c, A.pat.n, nbr, ma.W, outbits);
+  }
+  const int64_t nout = r.next.pat.nnzb;
+  const int oprec = mode == M_F64 ? P64 : P32;
+  r.next.pool = new_pool(c, oprec, nout);
+  r.parts = c.alloc(sizeof(double) * NPART * (size_t)(nout > 0 ? nout : 1));
+  Maps om = build_maps_general(c, r.next.pat, false, true, false);
+  Buf tiles;
+  // the 4 x 4 BF16x3 tiles pay off at the same density as in the symmetric
+  // square (there counted over the upper triangle)
+  const int tb = tile_edge(mode, nout / 2, nbr);
+  const int64_t ntiles = build_tiles(c, om.idxmap.as<int32_t>(), nbr, tiles, tb, true);
+  TileArgs ta;
+  ta.tb = tb;
+  ta.full = 1;
+  ta.xpool = A.pool->vals.p;
+  ta.xprec = A.pool->prec;
+  ta.idxmap = ma.idxmap.as<int32_t>();
+  ta.bits = ma.bits.as<uint32_t>();
+  ta.ypool = Bm.pool->vals.p;
+  ta.yidxmap = mbt.idxmap.as<int32_t>();
+  ta.ybits = mbt.bits.as<uint32_t>();
+  Buf xpack = pack_operand(c, A, mode), ypack = pack_operand(c, Bm, mode);
+  ta.xpack = xpack.p;
+  ta.ypack = ypack.p;
+  ta.npass = 1;
+  ta.gpool = G ? G->pool->vals.p : nullptr;
+  ta.gidxmap = G ? mg.idxmap.as<int32_t>() : nullptr;
+  ta.nbr = nbr;
+  ta.W = ma.W;
+  ta.oidx = om.idxmap.as<int32_t>();
+  ta.tiles = tiles.as<int32_t>();
+  ta.ntiles = ntiles;
+  ta.xcd_chunk = (ntiles + 7) / 8;
+  ta.opool = r.next.pool->vals.p;
+  ta.oprec = oprec;
+  ta.ca = ca;
+  ta.cb = cb;
+  ta.cc = cc;
+  ta.n = A.pat.n;
+  ta.parts = r.parts.as<double>();
+  EventPair ev;
+  if (verbose()) {
+    c.sync();
+    r.plan_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+  SP2_HIP(hipEventRecord(ev.a, c.stream));
+  if (mode == M_F64)
+    launch_square_f64_lds(c, ta);
+  else
+    launch_square_tile_bf16x3(c, ta);
+  SP2_HIP(hipEventRecord(ev.b, c.stream));
+  Buf sums = c.alloc(sizeof(double) * NPART);
+  launch_reduce_parts(c, ta.parts, nout, NPART, sums.as<double>());
+  c.d2h(r.sums, sums.p, sizeof(double) * NPART);
+  float ms = 0.0f;
+  SP2_HIP(hipEventElapsedTime(&ms, ev.a, ev.b));
+  r.kernel_s = 1e-3 * (double)ms;
+  c.kern_s[mode] += r.kernel_s;
+  c.kern_flops[mode] += r.sums[4] * 2.0 * B * B * B;
+  if (nout > 0) c.kern_launches[mode]++;
+  return r;
+}
+
+// general storage of a symmetric upper-BSR matrix (FP64)
+DMat expand_upper(Ctx &c, const DMat &U) {
+  if (U.pool->prec != P64) fail(SP2_ERR_INVALID_ARG, "expand_upper: FP64 values");
+  Maps m = build_maps(c, U.pat, false);  // symmetric: both orientations of every stored block
+  DMat o;
+  o.pat = pattern_from_bits(c, U.pat.n, m.nbr, m.W, m.bits);
+  o.pool = new_pool(c, P64, o.pat.nnzb);
+  launch_expand_upper(c, o.pat.row_of.as<int32_t>(), o.pat.col_idx.as<int32_t>(), o.pat.nnzb, m.nbr,
+                      m.idxmap.as<int32_t>(), U.pool->vals.as<double>(), o.pool->vals.as<double>());
   return o;
 }
 
@@ -729,6 +860,8 @@ struct Solver {
   sp2_options o{};
   int lowmode = M_F64;
   bool corr = false, low_to_end = false;
+  bool low_started = false;  // the low-precision squares have begun
+  bool tail32 = false;       // FP64-arithmetic tail on FP32-stored iterates (tail_storage = 1)
   Sched sch;
   int n_max = 0;
   // ---- adjoint tape
@@ -740,6 +873,7 @@ struct Solver {
   int i = 0;
   std::vector<double> e, t, trv, errF, errM, itime, iflops, ksq, alph{1.0}, taus;
   std::vector<int> p{-1}, precv;
+  std::vector<char> stor32v;  // X~_i stored in FP32
   std::vector<int64_t> nnzbv;
   int switch_iter = -1, n = -1, stop_reason = 0, status = SP2_OK;
   bool criterion_seen = false;  // the stopping test was evaluated at an admissible iteration
@@ -784,6 +918,10 @@ struct Solver {
   DMat host_load(const HostCopy &h);
   void correct_step();
   void note(const DMat &M) { cs.max_nnzb = std::max(cs.max_nnzb, M.pat.nnzb); }
+  // the low precision may square X~_k (its gap image has reached low_start_xi)
+  bool low_begins(int k) const {
+    return !sch.bounds || !(o.low_start_xi > 0.0) || k >= (int)sch.xi.size() || sch.xi[k] >= o.low_start_xi;
+  }
   // blocks of a correction intermediate dropped within the Frobenius budget beta
   void drop(DMat &M, const SquareOut &so) {
     note(M);
@@ -821,6 +959,10 @@ void Solver::begin(const sp2_bsr *Fin, int64_t n_occ_, double lmin_, double lmax
   if (!(o.corr_tol >= 0.0)) fail(SP2_ERR_INVALID_ARG, "corr_tol must be >= 0");
   if (o.corr_mem < 0) fail(SP2_ERR_INVALID_ARG, "corr_mem must be >= 0");
   if (o.adjoint_precision < -1 || o.adjoint_precision > 2) fail(SP2_ERR_INVALID_ARG, "unknown adjoint_precision");
+  if (!(o.low_start_xi >= 0.0 && o.low_start_xi < 1.0)) fail(SP2_ERR_INVALID_ARG, "low_start_xi must be in [0, 1)");
+  if (o.tail_storage != 0 && o.tail_storage != 1) fail(SP2_ERR_INVALID_ARG, "tail_storage must be 0 or 1");
+  if (o.tail_storage == 1 && o.correct > 0)
+    fail(SP2_ERR_INVALID_ARG, "tail_storage = 1 is not combined with the subspace correction");
   lowmode = o.precision == SP2_PREC_FP32 ? M_F32 : (o.precision == SP2_PREC_BF16X3 ? M_BF16X3 : M_F64);
   corr = o.correct > 0;
   // with the correction and no switch tolerance, or with a negative one, the
@@ -864,7 +1006,10 @@ void Solver::begin(const sp2_bsr *Fin, int64_t n_occ_, double lmin_, double lmax
     errM.push_back(tr.err_mixed);
     taus.push_back(sch.tau[0]);
   }
-  if (lowmode != M_F64) X = compact_values(c, X, P32);
+  if (lowmode != M_F64 && low_begins(0)) {
+    X = compact_values(c, X, P32);
+    low_started = true;
+  }
   switch_iter = lowmode != M_F64 ? -1 : 0;
 
   if (corr) {
@@ -982,7 +1127,7 @@ DMat Solver::host_load(const HostCopy &h) {
 // one iteration of Algorithm 2
 void Solver::iterate() {
   auto t_it = std::chrono::steady_clock::now();
-  const int mode = X.pool->prec == P32 ? lowmode : M_F64;
+  const int mode = (X.pool->prec == P32 && !tail32) ? lowmode : M_F64;
   if (tape) {
     tape->it.emplace_back();
     TapeIter &ti = tape->it.back();
@@ -1002,6 +1147,7 @@ void Solver::iterate() {
   nnzbv.push_back(X.pat.nnzb);
   max_nnzb = std::max(max_nnzb, X.pat.nnzb);
   precv.push_back(mode == M_F64 ? SP2_PREC_FP64 : o.precision);
+  stor32v.push_back(X.pool->prec == P32 ? 1 : 0);
 
   Maps m = build_maps(c, X.pat, true);
   const bool have_next = i < n_max;
@@ -1082,10 +1228,28 @@ void Solver::iterate() {
     taus.push_back(sch.tau[i + 1]);
   }
   const bool to_fp64 = (o.switch_tol > 0.0 && ei < o.switch_tol) || (!low_to_end && ei < low_floor(mode, trX));
-  if (Xn.pool->prec == P32 && to_fp64) {
+  if (Xn.pool->prec == P32 && to_fp64 && !tail32 && o.tail_storage == 1) {
+    // the FP64 tail keeps the FP32 storage: only the arithmetic changes
+    tail32 = true;
+    switch_iter = i + 1;
+    Xn = compact_if_sparse(c, std::move(Xn));
+  } else if (Xn.pool->prec == P32 && to_fp64 && !tail32) {
     Xn = compact_values(c, Xn, P64);
     sym_diag(c, Xn, 1.0);  // the FP64 tail starts from the symmetric part
     switch_iter = i + 1;
+  } else if (lowmode != M_F64 && !low_started && switch_iter < 0) {
+    // FP64 squares while the gap image is narrow; the low precision from the
+    // first X~_i whose gap reaches low_start_xi, unless e_i already calls for
+    // the FP64 tail (the run then stays in FP64)
+    if (o.switch_tol > 0.0 && ei < o.switch_tol) {
+      switch_iter = 0;
+      Xn = compact_if_sparse(c, std::move(Xn));
+    } else if (low_begins(i + 1)) {
+      Xn = compact_values(c, Xn, P32);
+      low_started = true;
+    } else {
+      Xn = compact_if_sparse(c, std::move(Xn));
+    }
   } else {
     Xn = compact_if_sparse(c, std::move(Xn));
   }
@@ -1369,7 +1533,9 @@ int Solver::finish(sp2_bsr **D_out, double *hest, double *lest, sp2_stats *st, s
   {
     std::vector<double> noise(n + 1);
     for (int k = 0; k <= n; ++k)
-      noise[k] = precv[k] == SP2_PREC_FP64 ? 0.0 : e_noise(precv[k] == SP2_PREC_FP32 ? M_F32 : M_BF16X3, trv[k]);
+      noise[k] = precv[k] == SP2_PREC_FP64
+                     ? (stor32v[k] ? e_noise(M_F32, trv[k]) : 0.0)  // FP32-stored tail: FP32 noise (an upper estimate)
+                     : e_noise(precv[k] == SP2_PREC_FP32 ? M_F32 : M_BF16X3, trv[k]);
     homo_lumo(sch, e, trv, p, alph, n, lmin, lmax, N, n_occ, h, l, &noise);
   }
   double bound = NaN;
@@ -1975,6 +2141,53 @@ int sp2_pair_product(sp2_ctx *ctx, const sp2_bsr *Xin, const sp2_bsr *Yin, const
       sums[0] = frob_norm(*ctx, so.next);
       sums[0] *= sums[0];
       sums[1] = so.sums[4] * 2.0 * B * B * B;
+    }
+    *out = export_bsr(*ctx, so.next);
+    return SP2_OK;
+  });
+}
+
+int sp2_general_from_upper(sp2_ctx *ctx, const sp2_bsr *Uin, sp2_bsr **G_out) {
+  return guarded(ctx, [&]() {
+    if (!G_out) fail(SP2_ERR_INVALID_ARG, "NULL output");
+    *G_out = nullptr;
+    DMat U = borrow_matrix(*ctx, Uin, "U");
+    check_finite(*ctx, Uin->val, Uin->nnzb * (int64_t)BB, "U");
+    *G_out = export_bsr(*ctx, expand_upper(*ctx, U));
+    return SP2_OK;
+  });
+}
+
+int sp2_general_product(sp2_ctx *ctx, const sp2_bsr *Ain, const sp2_bsr *Bin, const sp2_bsr *Gin, double a, double b,
+                        double cc, int precision, sp2_bsr **out, double sums[4]) {
+  return guarded(ctx, [&]() {
+    if (!out) fail(SP2_ERR_INVALID_ARG, "NULL output");
+    *out = nullptr;
+    if (precision != SP2_PREC_FP64 && precision != SP2_PREC_BF16X3)
+      fail(SP2_ERR_INVALID_ARG, "general product: precision must be SP2_PREC_FP64 or SP2_PREC_BF16X3");
+    DMat A = borrow_matrix(*ctx, Ain, "A", true);
+    DMat Bm = borrow_matrix(*ctx, Bin, "B", true);
+    if (Ain->n != Bin->n) fail(SP2_ERR_INVALID_ARG, "A and B differ in size");
+    check_finite(*ctx, Ain->val, Ain->nnzb * (int64_t)BB, "A");
+    check_finite(*ctx, Bin->val, Bin->nnzb * (int64_t)BB, "B");
+    DMat G;
+    if (Gin) {
+      G = borrow_matrix(*ctx, Gin, "G", true);
+      if (Gin->n != Ain->n) fail(SP2_ERR_INVALID_ARG, "G differs in size");
+      check_finite(*ctx, Gin->val, Gin->nnzb * (int64_t)BB, "G");
+    }
+    const int mode = precision == SP2_PREC_FP64 ? M_F64 : M_BF16X3;
+    if (mode != M_F64) {
+      A = compact_values(*ctx, A, P32);
+      Bm = compact_values(*ctx, Bm, P32);
+      if (Gin) G = compact_values(*ctx, G, P32);
+    }
+    SquareOut so = general_product(*ctx, A, Bm, Gin ? &G : nullptr, a, b, cc, mode);
+    if (sums) {
+      sums[0] = so.sums[0];
+      sums[1] = so.sums[1];
+      sums[2] = so.sums[2];
+      sums[3] = so.sums[4] * 2.0 * B * B * B;
     }
     *out = export_bsr(*ctx, so.next);
     return SP2_OK;

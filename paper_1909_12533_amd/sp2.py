@@ -471,6 +471,37 @@ def pair_product(X: BsrMatrix, Y: BsrMatrix, G: BsrMatrix | None = None, sign=1,
     return r, list(sums)
 
 
+def general_from_upper(U: BsrMatrix, ctx: Context | None = None):
+    """General (full-pattern) storage of the symmetric matrix held by the
+    upper-BSR U; see sp2_general_from_upper in sp2dm.h."""
+    ctx = ctx or context(U.device.index)
+    out = C.POINTER(L.sp2_bsr)()
+    s = U._struct()
+    ctx._check(ctx.lib.sp2_general_from_upper(ctx.h, C.byref(s), C.byref(out)))
+    r = ctx.take(out)
+    ctx.trim()
+    return r
+
+
+def general_product(A: BsrMatrix, B: BsrMatrix, G: BsrMatrix | None = None, a=0.0, b=0.0, c=1.0, precision="fp64",
+                    ctx: Context | None = None):
+    """a I + b G + c A B for matrices in general storage, on the block
+    pattern of A B (joined with G's, and the diagonal when a != 0); returns
+    (out, [||G - A B||_F^2, tr G, tr A B, flops]); see sp2_general_product in
+    sp2dm.h."""
+    ctx = ctx or context(A.device.index)
+    out = C.POINTER(L.sp2_bsr)()
+    sums = (C.c_double * 4)()
+    sa, sb = A._struct(), B._struct()
+    sg = G._struct() if G is not None else None
+    p = _PREC[precision] if isinstance(precision, str) else int(precision)
+    ctx._check(ctx.lib.sp2_general_product(ctx.h, C.byref(sa), C.byref(sb), C.byref(sg) if sg is not None else None,
+                                           float(a), float(b), float(c), p, C.byref(out), sums))
+    r = ctx.take(out)
+    ctx.trim()
+    return r, list(sums)
+
+
 def matrix_norms(A: BsrMatrix, coarse_bs=4096, ctx: Context | None = None):
     """(||A||_F, ||A||_M) of the symmetric matrix held by A's upper blocks;
     ||A||_M is the Frob-Inf norm with coarse_bs x coarse_bs submatrices."""

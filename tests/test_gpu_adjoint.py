@@ -159,4 +159,66 @@ def test_mixed_tape_adjoint_arithmetic(gpu_lib):
         assert lhs == pytest.approx(rhs, rel=dot_tol[adj])
     assert rel(g[-1], g["fp64"]) <= 1e-3
     assert rel(g["fp32"], g["fp64"]) <= 1e-5
-    assert rel(g["fp64"], g64) <= 5e-2
+    # (the distance to the FP64 forward's gradient is held to a stated bound
+    # against the oracle's adjoint at tau = 1e-6 below; at tau = 1e-2 the two
+    # trajectories also differ in their truncation masks)
+    assert np.isfinite(g64).all()
+
+
+@pytest.fixture(scope="module")
+def l8_adjoint():
+    """The 8 x 8 x 8 x 4 lattice (N = 2048), SP2ACC, tau = 1e-6 Frob-Inf(512):
+    the oracle's FP64 expansion and its adjoint (gradient of tr(W D))"""
+    Fh, info = lattice_fock(8, seed=0)
+    Fd = bsr_to_dense(Fh)
+    no = info["n_occ"]
+    lmin, lmax = O.gershgorin_bounds(Fd)
+    kw = dict(accel=True, trunc_norm="frobinf", tau_fixed=1e-6, coarse_bs=512)
+    ref = O.sp2(Fd, no, lmin, lmax, -0.31, 0.33, keep_tape=True, **kw)
+    Wh = random_sym_on_pattern(Fh, 1.0, seed=2)
+    g_ref = O.vjp(ref, Fd, bsr_to_dense(Wh))
+    sch = O.schedule(lmin, lmax, -0.31, 0.33, accel=True, tau_fixed=1e-6)
+    xi = [1.0 - q - l for q, l in zip(sch.q, sch.l)]
+    return Fh, no, lmin, lmax, kw, ref, Wh, g_ref, xi
+
+
+def test_fp64_vjp_matches_oracle_l8(gpu_lib, l8_adjoint):
+    sp2 = gpu_lib
+    Fh, no, lmin, lmax, kw, ref, Wh, g_ref, xi = l8_adjoint
+    r = sp2.density(sp2.BsrMatrix.from_host(Fh), no, lmin, lmax, -0.31, 0.33, record_tape=True, **kw)
+    assert r.n_iter == ref.n and list(r.iters["nnzb"]) == list(ref.nnzb)
+    g = to_dense(r.tape.vjp(sp2.BsrMatrix.from_host(Wh)))
+    print(f"FP64 gradient vs oracle: {rel(g, g_ref):.3e}")
+    assert rel(g, g_ref) <= 1e-10
+
+
+# ||g - g_oracle|| / ||g_oracle|| measured for low-precision forwards on the
+# 8^3 lattice (low_start_xi: FP64 squares while the gap image xi_i is below
+# it); the test allows twice that
+MIXED_GRAD_L8 = {("bf16x3", 0.0): 6.7e-5, ("bf16x3", 0.1): 1.9e-5, ("fp32", 0.0): 1.0e-5}
+
+
+@pytest.mark.parametrize("prec,xi0", sorted(MIXED_GRAD_L8))
+def test_mixed_vjp_against_oracle_l8(gpu_lib, l8_adjoint, prec, xi0):
+    """Gradient of tr(W D) through a low-precision forward (FP64 tail from
+    e_i < 1e-3) against the oracle's FP64 one.  The difference comes from the
+    low-precision trajectory; rounding at the first, narrow-gap iterations
+    (small xi_i) turns the occupied subspace the most, which an FP64 prefix
+    (low_start_xi) removes."""
+    sp2 = gpu_lib
+    Fh, no, lmin, lmax, kw, ref, Wh, g_ref, xi = l8_adjoint
+    F = sp2.BsrMatrix.from_host(Fh)
+    r = sp2.density(F, no, lmin, lmax, -0.31, 0.33, record_tape=True, precision=prec, switch_tol=1e-3,
+                    low_start_xi=xi0, **kw)
+    k0 = next(k for k, x in enumerate(xi) if x >= xi0)
+    prs = [int(v) for v in r.iters["precision"]]
+    low = 1 if prec == "fp32" else 2
+    assert prs[:k0] == [0] * k0 and prs[k0] == low
+    assert r.switch_iter > k0 and prs[k0:r.switch_iter] == [low] * (r.switch_iter - k0)
+    assert all(v == 0 for v in prs[r.switch_iter:])
+    assert np.array_equal(to_dense(r.tape.replay(F)), to_dense(r.D))
+    g = to_dense(r.tape.vjp(sp2.BsrMatrix.from_host(Wh)))
+    err = rel(g, g_ref)
+    print(f"{prec} low_start_xi={xi0}: first low square {k0}, switch {r.switch_iter}, n={r.n_iter}; "
+          f"gradient vs oracle {err:.3e}")
+    assert err <= 2 * MIXED_GRAD_L8[(prec, xi0)]

@@ -189,6 +189,59 @@ def test_mixed_fp64_tail_error(gpu_lib, l8_oracle, prec):
     assert np.linalg.norm(D @ D - D) <= 1e-9
 
 
+# ||D - D_FP64-stored tail||_F measured for the FP32-stored tail on the 8^3
+# lattice; the test allows twice that
+TAIL32_L8_DIFF = {"fp32": 1e-3, "bf16x3": 1e-3}
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_fp32_stored_fp64_tail(gpu_lib, l8_oracle, prec):
+    """tail_storage = 1: the FP64 tail multiplies FP32-stored iterates in FP64
+    arithmetic.  Same low-precision phase and switch as the FP64-stored tail;
+    the tail squares are FP64 (precision code 0); idempotency reaches the FP32
+    storage floor (the rounding E of an iterate to FP32 has ||E||_F <=
+    2^-24 ||X||_F, and X - X^2 picks up E's occupied-occupied and
+    virtual-virtual parts), the trace error stays within sqrt(N) ||D^2 - D||_F
+    (the eigenvalue bound of the trace error model), the result is within
+    twice its measured distance of the FP64-stored tail's, and the recorded
+    map replays bit for bit."""
+    sp2 = gpu_lib
+    Fh, Fd, no, lmin, lmax, lam, ref = l8_oracle
+    F = sp2.BsrMatrix.from_host(Fh)
+    kw = dict(trunc_norm="frobinf", tau_fixed=1e-6, coarse_bs=512, precision=prec)
+    r64 = sp2.density(F, no, lmin, lmax, -0.31, 0.33, **kw)
+    r = sp2.density(F, no, lmin, lmax, -0.31, 0.33, tail_storage=1, record_tape=True, **kw)
+    code = {"fp32": 1, "bf16x3": 2}[prec]
+    assert r.switch_iter == r64.switch_iter >= 1
+    assert set(r.iters["precision"][: r.switch_iter]) == {code}
+    assert set(r.iters["precision"][r.switch_iter:]) == {0}
+    assert np.array_equal(r.iters["e"][: r.switch_iter], r64.iters["e"][: r64.switch_iter])
+    D, D64 = to_dense(r.D), to_dense(r64.D)
+    N = D.shape[0]
+    idem = np.linalg.norm(D @ D - D)
+    floor = 2.0 ** -24 * np.sqrt(no)
+    diff = np.linalg.norm(D - D64)
+    print(f"{prec} FP32-stored tail: n = {r.n_iter} ({r.stop_reason}), e_n = {r.iters['e'][-1]:.3e}, "
+          f"||D^2 - D||_F = {idem:.3e} (storage floor {floor:.2e}), |tr D - n_occ| = {abs(np.trace(D) - no):.3e}, "
+          f"||D - D_tail64||_F = {diff:.3e}, ||D - D_oracle||_F = {np.linalg.norm(D - ref.D):.3e}")
+    assert r.status == 0
+    assert idem <= r.iters["e"][-1] + 4 * floor
+    assert r.iters["e"][-1] <= r64.iters["e"][-1] + 4 * floor
+    assert abs(np.trace(D) - no) <= np.sqrt(N) * idem + 1e-9
+    assert diff <= 2 * TAIL32_L8_DIFF[prec]
+    assert np.array_equal(to_dense(r.tape.replay(F)), D)
+
+
+def test_tail_storage_invalid(gpu_lib, l8_oracle):
+    sp2 = gpu_lib
+    Fh, Fd, no, lmin, lmax, lam, ref = l8_oracle
+    F = sp2.BsrMatrix.from_host(Fh)
+    with pytest.raises(RuntimeError, match="tail_storage"):
+        sp2.density(F, no, lmin, lmax, -0.31, 0.33, precision="fp32", tail_storage=2)
+    with pytest.raises(RuntimeError, match="tail_storage"):
+        sp2.density(F, no, lmin, lmax, -0.31, 0.33, precision="fp32", tail_storage=1, correct=1)
+
+
 @pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
 def test_mixed_homo_lumo_valid_and_tight(gpu_lib, l8_oracle, prec):
     """Step 3 on a mixed run: low-precision e_i enter above ten times their
