@@ -434,7 +434,7 @@ def run1_bounds(config, L, tau):
     r = d.get(config)
     if not r or r.get("L") != L or r.get("tau") != tau:
         return None
-    return r["homo_ub"], r["lumo_lb"]
+    return r["homo_ub"], r["lumo_lb"], r.get("bounds_from")
 
 
 def main():
@@ -521,8 +521,8 @@ def main():
         hub, llb = (float(x) for x in args.bounds.split(","))
         bounds_from = "given"
     elif not args.run1 and run1_bounds(args.config, L, tau):
-        hub, llb = run1_bounds(args.config, L, tau)
-        bounds_from = "run 1 (trace-correcting FP64 run) recorded in bench_run1.json"
+        hub, llb, note = run1_bounds(args.config, L, tau)
+        bounds_from = note or "run 1 (trace-correcting FP64 run) recorded in bench_run1.json"
     else:
         t = time.perf_counter()
         r1o = dict(opts)

@@ -291,7 +291,10 @@ __global__ __launch_bounds__(64 * NW, (NW == 4 && sizeof(T) == 4) ? 2 : 1) void 
 // row-major order, tiles row-major inside a super-tile.  Linear id
 // ((STI * nst + STJ) * ST + ti) * ST + tj with TI = STI * ST + ti,
 // TJ = STJ * ST + tj.
-constexpr int ST = 4;
+#ifndef SP2_TILE_ST
+#define SP2_TILE_ST 4
+#endif
+constexpr int ST = SP2_TILE_ST;
 
 __device__ inline bool tile_of(int64_t id, int ntr, int nst, bool full, int &TI, int &TJ) {
   const int tj = (int)(id % ST);

@@ -51,9 +51,12 @@ template <typename T> struct Stage {
 // it the contiguous chunk [x * chunk, (x + 1) * chunk) of the (super-tile
 // ordered) tile list keeps tiles that share operand panels on the same L2.
 // Returns -1 for the padding workgroups of the last chunk.
+#ifndef SP2_XCD_MAP
+#define SP2_XCD_MAP 1
+#endif
 __device__ inline int64_t xcd_tile(const TileArgs &a) {
   const int64_t b = blockIdx.x;
-  const int64_t t = (b % 8) * a.xcd_chunk + b / 8;
+  const int64_t t = SP2_XCD_MAP ? (b % 8) * a.xcd_chunk + b / 8 : b;
   return t < a.ntiles ? t : -1;
 }
 
