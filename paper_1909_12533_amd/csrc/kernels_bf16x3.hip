@@ -300,11 +300,15 @@ __global__ __launch_bounds__(512, 2) void k_square_tile4_bf16x3(TileArgs a) {
 
   // K over the union of the 16 blocks' K sets (second pass: operands
   // swapped); the right operand's slots are read along row J of the symmetric
-  // slot map.  Once exhausted the scan keeps returning false.
+  // slot map.  scan() finds the next non-empty bitmap word (its loads are
+  // waited for at once; once per 32 K on dense patterns) and keeps returning
+  // false when the K sets are exhausted; issue_k() takes the next K of the
+  // word and only issues the loads of its slots, which fin_k() makes
+  // wave-uniform after the MFMAs of a k half, so their latency is hidden.
   const uint32_t *lbits = a.bits, *rbits = GEN ? a.ybits : a.bits;
   int wi = -1, pass = 0;
   uint32_t mask = 0u;
-  auto next_k = [&](Stage4 &q) -> bool {
+  auto scan = [&]() -> bool {
     while (mask == 0u) {
       ++wi;
       if (wi >= W) {
@@ -326,24 +330,36 @@ __global__ __launch_bounds__(512, 2) void k_square_tile4_bf16x3(TileArgs a) {
       }
       mask = (uint32_t)__builtin_amdgcn_readfirstlane((int)(ra & rb));
     }
+    return true;
+  };
+  // a zero the compiler takes for a per-lane value: the slot loads then stay
+  // vector loads into registers, unwaited until fin_k
+  int vz = 0;
+  asm volatile("" : "+v"(vz));
+  const int Rd = wave < 4 ? I0 + wave : J0 + wave - 4;  // the operand this wave loads
+  auto issue_k = [&](Stage4 &q) {  // requires mask != 0
     const int K = wi * 32 + __builtin_ctz(mask);
     mask &= mask - 1u;
     q.K = K;
     q.kp = pass;
-    const int32_t *li = (GEN && pass) ? a.yidxmap : a.idxmap;
-    const int32_t *ri = GEN ? (pass ? a.idxmap : a.yidxmap) : a.idxmap;
+    const int32_t *li = ((GEN && pass) ? a.yidxmap : a.idxmap) + vz;
+    const int32_t *ri = (GEN ? (pass ? a.idxmap : a.yidxmap) : a.idxmap) + vz;
     const bool la = GEN && (pass ? a.yanti : a.xanti), rn = GEN && (pass ? a.xanti : a.yanti);
     const bool ng = GEN && pass && a.neg2;
     constexpr uint32_t SGN2 = 0x80008000u;
-    q.sa = I < nbr ? __builtin_amdgcn_readfirstlane(li[(int64_t)I * nbr + K]) : -1;
-    q.sb0 = Jb0 < nbr ? __builtin_amdgcn_readfirstlane(ri[(int64_t)Jb0 * nbr + K]) : -1;
-    q.sb1 = Jb1 < nbr ? __builtin_amdgcn_readfirstlane(ri[(int64_t)Jb1 * nbr + K]) : -1;
+    q.sa = li[(int64_t)(I < nbr ? I : 0) * nbr + K];
+    q.sb0 = ri[(int64_t)(Jb0 < nbr ? Jb0 : 0) * nbr + K];
+    q.sb1 = ri[(int64_t)(Jb1 < nbr ? Jb1 : 0) * nbr + K];
+    q.sd = (wave < 4 ? li : ri)[(int64_t)(Rd < nbr ? Rd : 0) * nbr + K];
     q.ga = ((la && I > K) != ng) ? SGN2 : 0u;
     q.gb0 = (rn && K > Jb0) ? SGN2 : 0u;
     q.gb1 = (rn && K > Jb1) ? SGN2 : 0u;
-    const int Rd = wave < 4 ? I0 + wave : J0 + wave - 4;  // the operand this wave loads
-    q.sd = Rd < nbr ? __builtin_amdgcn_readfirstlane((wave < 4 ? li : ri)[(int64_t)Rd * nbr + K]) : -1;
-    return true;
+  };
+  auto fin_k = [&](Stage4 &q) {  // rows past the last block row read row 0: -1
+    q.sa = I < nbr ? __builtin_amdgcn_readfirstlane(q.sa) : -1;
+    q.sb0 = Jb0 < nbr ? __builtin_amdgcn_readfirstlane(q.sb0) : -1;
+    q.sb1 = Jb1 < nbr ? __builtin_amdgcn_readfirstlane(q.sb1) : -1;
+    q.sd = Rd < nbr ? __builtin_amdgcn_readfirstlane(q.sd) : -1;
   };
 
   // k half kh of the 8 operand images of q into stage st: 64 load
@@ -414,13 +430,24 @@ __global__ __launch_bounds__(512, 2) void k_square_tile4_bf16x3(TileArgs a) {
   };
 
   Stage4 q, qn;
-  if (next_k(q)) {
+  if (scan()) {
+    issue_k(q);
+    fin_k(q);
     dma(q, 0, S0);
     while (true) {
       __syncthreads();  // k half 0 of K in S0 (every wave waited for its loads); S1 free
       dma(q, 1, S1);
+      // the next K of the current bitmap word: its slot loads run under the MFMAs
+      bool more = mask != 0u;
+      if (more) issue_k(qn);
       compute(q, S0);
-      const bool more = next_k(qn);
+      if (more) {
+        fin_k(qn);
+      } else if (scan()) {  // a new bitmap word (its loads waited for here)
+        more = true;
+        issue_k(qn);
+        fin_k(qn);
+      }
       __syncthreads();  // k half 1 in S1; S0 free
       if (more) dma(qn, 0, S0);
       compute(q, S1);
