@@ -131,6 +131,15 @@ inline double e_noise(int low_kind, double trX) {
   return kappa * std::sqrt(std::fmax(trX, 1.0));
 }
 
+// Noise of e_i for an FP64 square of an FP32-stored iterate (the FP32-stored
+// FP64 tail): e_i is exact for the stored X~, which differs from the iterate
+// of the recursion by its FP32 rounding E, ||E||_F <= 2^-24 ||X~||_F, and
+// |e(X~ + E) - e(X~)| <= ||E|| (1 + 2 ||X~||_2 + ||E||) ~ 3 ||E||_F; near a
+// projector ||X~||_F^2 ~ tr X~.
+inline double e_noise_fp32_storage(double trX) {
+  return 3.0 * 5.9604644775390625e-08 * std::sqrt(std::fmax(trX, 1.0));
+}
+
 // Step 3 estimates.  e[i], tr[i] of X~_i; p, alpha of the run; sched holds
 // the forward bounds in bounds mode.  Returns {homo_ub, lumo_lb} (NaN if none).
 // noise[i] (optional): rounding noise of a low-precision e_i (0 for FP64).

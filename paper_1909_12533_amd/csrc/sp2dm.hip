@@ -1534,7 +1534,7 @@ int Solver::finish(sp2_bsr **D_out, double *hest, double *lest, sp2_stats *st, s
     std::vector<double> noise(n + 1);
     for (int k = 0; k <= n; ++k)
       noise[k] = precv[k] == SP2_PREC_FP64
-                     ? (stor32v[k] ? e_noise(M_F32, trv[k]) : 0.0)  // FP32-stored tail: FP32 noise (an upper estimate)
+                     ? (stor32v[k] ? e_noise_fp32_storage(trv[k]) : 0.0)
                      : e_noise(precv[k] == SP2_PREC_FP32 ? M_F32 : M_BF16X3, trv[k]);
     homo_lumo(sch, e, trv, p, alph, n, lmin, lmax, N, n_occ, h, l, &noise);
   }

@@ -230,6 +230,12 @@ def test_fp32_stored_fp64_tail(gpu_lib, l8_oracle, prec):
     assert abs(np.trace(D) - no) <= np.sqrt(N) * idem + 1e-9
     assert diff <= 2 * TAIL32_L8_DIFF[prec]
     assert np.array_equal(to_dense(r.tape.replay(F)), D)
+    # Step 3 with the FP32-storage noise of the tail's e_i: valid bounds
+    homo, lumo = lam[no - 1], lam[no]
+    print(f"homo/lumo estimates {r.homo_est:.5f} / {r.lumo_est:.5f} (exact {homo:.5f} / {lumo:.5f}; "
+          f"FP64-stored tail {r64.homo_est:.5f} / {r64.lumo_est:.5f})")
+    assert not np.isnan(r.homo_est) and not np.isnan(r.lumo_est)
+    assert homo <= r.homo_est + 1e-9 and r.lumo_est - 1e-9 <= lumo
 
 
 def test_tail_storage_invalid(gpu_lib, l8_oracle):
