@@ -87,6 +87,7 @@ extern "C" {
 #define SP2_STOP_CRITERION 1   /* e_i > C e_{i-2}^2 with p_i != p_{i-1} (Algorithm 2) */
 #define SP2_STOP_IDEMPOTENCY 2 /* e_i <= idem_stop */
 #define SP2_STOP_NMAX 3        /* i = n_max */
+#define SP2_STOP_NOISE_FLOOR 4 /* low_floor_stop: a low-precision e_i below ten times its rounding noise */
 
 typedef struct sp2_ctx sp2_ctx;
 typedef struct sp2_tape sp2_tape;
@@ -146,6 +147,11 @@ typedef struct {
                               squares, an idempotency floor of about the FP32 rounding of the iterate,
                               ~2^-24 ||X||_F, instead of the FP32 squares' accumulation noise); not
                               combined with the correction */
+  int32_t low_floor_stop;  /* 1: an expansion that stays in the low precision to its end (switch_tol <= 0 with
+                              the correction, or < 0) stops at the first e_i below ten times its rounding
+                              noise (the level from which the FP64 tail would start: the low-precision
+                              squares no longer resolve convergence), before the criterion of Algorithm 2,
+                              which needs e_i to stop decreasing; 0 (default): by the criterion */
 } sp2_options;
 
 /* Per-run statistics.  Arrays are HOST arrays owned by the caller, each of
@@ -201,7 +207,7 @@ const char *sp2_version(void);
  * n_max_cap 100, coarse_bs 4096, gamma 1e-3, tau_fixed 0, idem_stop 0,
  * no tape, no subspace correction (corr_purify 2, corr_tol 1e-9, corr_mem 0),
  * adjoint_precision -1, corr_deriv_tol 0, corr_mcweeny 0, corr_host_mem 0, low_start_xi 0,
- * tail_storage 0. */
+ * tail_storage 0, low_floor_stop 0. */
 void sp2_options_default(sp2_options *opt);
 
 /* Create a context on HIP device `device` issuing all work on `hip_stream`

@@ -18,7 +18,7 @@ SP2_WARN_TRACE = 2
 
 PREC_FP64, PREC_FP32, PREC_BF16X3 = 0, 1, 2
 TRUNC_NONE, TRUNC_FROB, TRUNC_FROBINF = 0, 1, 2
-STOP_CRITERION, STOP_IDEMPOTENCY, STOP_NMAX = 1, 2, 3
+STOP_CRITERION, STOP_IDEMPOTENCY, STOP_NMAX, STOP_NOISE_FLOOR = 1, 2, 3, 4
 
 # names of every exported entry point declared in include/sp2dm.h
 EXPORTS = [
@@ -67,6 +67,7 @@ class sp2_options(C.Structure):
         ("corr_host_mem", C.c_int64),
         ("low_start_xi", C.c_double),
         ("tail_storage", C.c_int32),
+        ("low_floor_stop", C.c_int32),
     ]
 
 

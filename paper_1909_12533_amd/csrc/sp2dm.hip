@@ -961,6 +961,7 @@ void Solver::begin(const sp2_bsr *Fin, int64_t n_occ_, double lmin_, double lmax
   if (o.adjoint_precision < -1 || o.adjoint_precision > 2) fail(SP2_ERR_INVALID_ARG, "unknown adjoint_precision");
   if (!(o.low_start_xi >= 0.0 && o.low_start_xi < 1.0)) fail(SP2_ERR_INVALID_ARG, "low_start_xi must be in [0, 1)");
   if (o.tail_storage != 0 && o.tail_storage != 1) fail(SP2_ERR_INVALID_ARG, "tail_storage must be 0 or 1");
+  if (o.low_floor_stop != 0 && o.low_floor_stop != 1) fail(SP2_ERR_INVALID_ARG, "low_floor_stop must be 0 or 1");
   if (o.tail_storage == 1 && o.correct > 0)
     fail(SP2_ERR_INVALID_ARG, "tail_storage = 1 is not combined with the subspace correction");
   lowmode = o.precision == SP2_PREC_FP32 ? M_F32 : (o.precision == SP2_PREC_BF16X3 ? M_BF16X3 : M_F64);
@@ -1182,6 +1183,11 @@ void Solver::iterate() {
     } else if (o.idem_stop > 0.0 && e[i] <= o.idem_stop) {
       stop = true;
       stop_reason = SP2_STOP_IDEMPOTENCY;
+    } else if (low_window && o.low_floor_stop && i >= 2 && ei < low_floor(mode, trX)) {
+      // the low-precision squares cannot resolve e below this level: the
+      // next iterates would only repeat it until the criterion fires
+      stop = true;
+      stop_reason = SP2_STOP_NOISE_FLOOR;
     }
   }
   if (!stop && i == n_max) {

@@ -20,7 +20,8 @@ from . import _lib as L
 _PREC = {"fp64": L.PREC_FP64, "fp32": L.PREC_FP32, "bf16x3": L.PREC_BF16X3}
 _PREC_NAME = {v: k for k, v in _PREC.items()}
 _NORM = {"none": L.TRUNC_NONE, "frob": L.TRUNC_FROB, "frobinf": L.TRUNC_FROBINF}
-_STOP = {L.STOP_CRITERION: "criterion", L.STOP_IDEMPOTENCY: "idempotency", L.STOP_NMAX: "n_max", 0: ""}
+_STOP = {L.STOP_CRITERION: "criterion", L.STOP_IDEMPOTENCY: "idempotency", L.STOP_NMAX: "n_max",
+         L.STOP_NOISE_FLOOR: "noise_floor", 0: ""}
 
 
 class Sp2Error(RuntimeError):

@@ -69,19 +69,35 @@ def test_fp64_matches_oracle_l12(gpu_lib, l12):
     assert r.lumo_est == pytest.approx(ref.lumo_lb_est, abs=1e-9)
 
 
-@pytest.mark.parametrize("prec,mcweeny", [("bf16x3", 1), ("bf16x3", 0), ("fp32", 1)])
-def test_corrected_low_precision_matches_oracle_l12(gpu_lib, l12, prec, mcweeny):
+@pytest.mark.parametrize("prec,mcweeny,fast", [("bf16x3", 1, False), ("bf16x3", 0, False), ("fp32", 1, False),
+                                               ("bf16x3", 1, True)])
+def test_corrected_low_precision_matches_oracle_l12(gpu_lib, l12, prec, mcweeny, fast):
+    """fast: the benchmark's settings (the expansion stops at its noise floor,
+    derivative steps stop at e_k < 0.1)."""
     sp2 = gpu_lib
     Fh, no, lmin, lmax, h, lu, ref = l12
+    extra = dict(low_floor_stop=1, corr_deriv_tol=0.1) if fast else {}
     r = sp2.density(sp2.BsrMatrix.from_host(Fh), no, lmin, lmax, h, lu, precision=prec, switch_tol=0.0,
-                    correct=1, corr_mcweeny=mcweeny, corr_purify=1 if mcweeny else 2, **KW)
+                    correct=1, corr_mcweeny=mcweeny, corr_purify=1 if mcweeny else 2, **extra, **KW)
     D = to_dense(r.D)
     err = np.linalg.norm(D - ref.D)
-    print(f"{prec} + correction (mcweeny={mcweeny}): ||D - D_oracle||_F = {err:.3e}, status {r.status} "
-          f"({r.stop_reason}), n={r.n_iter}, {r.correction}")
+    print(f"{prec} + correction (mcweeny={mcweeny}, fast={fast}): ||D - D_oracle||_F = {err:.3e}, status "
+          f"{r.status} ({r.stop_reason}), n={r.n_iter}, {r.correction}")
     assert r.status == 0
+    if fast:  # the first e_i below ten times the BF16x3 rounding noise ends the expansion
+        assert r.stop_reason == "noise_floor"
+        nu = 1.6e-5 * np.sqrt(r.iters["trace"][-1])
+        assert r.iters["e"][-1] < 10 * nu and all(r.iters["e"][2:-1] >= 10 * 1.6e-5 * np.sqrt(
+            np.maximum(r.iters["trace"][2:-1], 1.0)))
     assert err <= 1e-5
-    assert abs(np.trace(D) - no) <= 1e-6
+    if fast:
+        # one McWeeny step maps an eigenvalue's distance d from {0, 1} to
+        # 3 d^2 - 2 d^3, and sum d^2 ~ e^2 with e = ||P - P^2||_F of its input:
+        # |tr D - n_occ| <= 3 e^2 (the expansion stopped earlier, e is larger)
+        e = r.correction["corr_e_last"]
+        assert abs(np.trace(D) - no) <= 3.3 * e * e + 1e-9
+    else:
+        assert abs(np.trace(D) - no) <= 1e-6
 
 
 # measured ||D - D_oracle||_F of the FP64-tail runs (the bound is twice that)
