@@ -259,6 +259,7 @@ struct TileArgs {
 int64_t build_tiles(Ctx &c, const int32_t *oidx, int nbr, Buf &tiles, int tb = 2, bool full = false);
 void launch_square_tile(Ctx &c, int mode, const TileArgs &a);
 // FP64 squares and products with operands loaded straight to LDS (kernels_f64.hip)
+// (FP64 operands, or FP32-stored ones widened to FP64 at the fragment reads)
 void launch_square_f64_lds(Ctx &c, const TileArgs &a);
 void launch_square_tile_bf16x3(Ctx &c, const TileArgs &a);  // kernels_bf16x3.hip
 // split the stored blocks of an FP32 pool into bf16 hi/lo images of the block

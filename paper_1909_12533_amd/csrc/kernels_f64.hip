@@ -1,6 +1,7 @@
-// FP64 square and two-operand products with operands loaded straight to LDS
-// (the symmetric square of Algorithm 2 in FP64, the method's reference
-// arithmetic; the products X Y +- Y X of the adjoint and the correction).
+// FP64 squares and two-operand products with operands loaded straight to LDS
+// (the symmetric square of Algorithm 2 in the method's reference arithmetic;
+// the products X Y +- Y X of the adjoint and the correction; the FP64 square
+// of FP32-stored iterates, widened to FP64 at the fragment reads).
 //
 // One workgroup of four waves per 2 x 2 tile of output blocks; wave w owns the
 // whole 64 x 64 block (I0 + w / 2, J0 + w % 2) in 4 x 4 MFMA accumulator tiles.
@@ -40,40 +41,79 @@ namespace {
 using namespace dev;
 
 
-constexpr int QS = 64 * 16;  // doubles per operand quarter-slice (8 KB)
-
-// quarter slices: kcol [64 rows][16 k] (128-byte rows, chunk c of row r at
-// position c ^ ((r >> 1) & 7)); krow [16 k][64 columns] (512-byte rows, chunk
-// c of k-row kr at position c ^ (8 ((kr >> 2) & 1)))
-__device__ __forceinline__ int qcol_pos(int r, int c) { return c ^ ((r >> 1) & 7); }
-__device__ __forceinline__ int qrow_pos(int kr, int c) { return c ^ (((kr >> 2) & 1) << 3); }
+// Staging geometry of a quarter slice (16 k) of one 64 x 64 operand block
+// stored as TI: kcol [64 rows][16 k] (the operand used untransposed along k),
+// krow [16 k][64 columns] (used transposed), 16-byte chunks XOR-swizzled so
+// that the fragment reads of the 16 lanes of a lane group hit distinct banks.
+// One load instruction writes 1 KB of LDS contiguously (lane l at byte 16 l);
+// each lane fetches the global chunk that belongs at its position.
+template <typename TI> struct QGeom;
+template <> struct QGeom<double> {
+  static constexpr int BYTES = 64 * 16 * 8;  // 8 KB per operand quarter
+  static constexpr int LOADS = BYTES / 1024;
+  static constexpr int PAIR_KCOL = 8, PAIR_KROW = 512;  // byte distance of elements k and k + 1
+  // kcol: 128-byte rows, chunk c of row r at c ^ ((r >> 1) & 7); krow:
+  // 512-byte rows, chunk c of k-row kr at c ^ (8 ((kr >> 2) & 1))
+  __device__ static int col_pos(int r, int c) { return c ^ ((r >> 1) & 7); }
+  __device__ static int row_pos(int kr, int c) { return c ^ (((kr >> 2) & 1) << 3); }
+  // byte offset of element (r, k), k even
+  __device__ static int frag(bool kcol, int r, int k) {
+    return kcol ? 16 * (r * 8 + col_pos(r, k >> 1)) : 8 * (k * 64 + row_pos(k, r >> 1) * 2 + (r & 1));
+  }
+  // global 16-byte chunk (within the block) that load i of lane l brings to quarter kq
+  __device__ static int gchunk(bool kcol, int kq, int i, int lane) {
+    if (kcol) {
+      const int r = 8 * i + (lane >> 3), p = lane & 7;
+      return r * 32 + 8 * kq + col_pos(r, p);
+    }
+    const int kr = 2 * i + (lane >> 5), p = lane & 31;
+    return (16 * kq + kr) * 32 + row_pos(kr, p);
+  }
+};
+template <> struct QGeom<float> {
+  static constexpr int BYTES = 64 * 16 * 4;  // 4 KB per operand quarter
+  static constexpr int LOADS = BYTES / 1024;
+  static constexpr int PAIR_KCOL = 4, PAIR_KROW = 256;
+  // kcol: 64-byte rows, chunk c (4 k) of row r at c ^ ((r >> 2) & 3); krow:
+  // 256-byte rows, chunk c (4 columns) of k-row kr at c ^ (4 ((kr >> 2) & 3))
+  __device__ static int col_pos(int r, int c) { return c ^ ((r >> 2) & 3); }
+  __device__ static int row_pos(int kr, int c) { return c ^ (((kr >> 2) & 3) << 2); }
+  __device__ static int frag(bool kcol, int r, int k) {
+    return kcol ? 16 * (r * 4 + col_pos(r, k >> 2)) + 4 * (k & 3) : 16 * (k * 16 + row_pos(k, r >> 2)) + 4 * (r & 3);
+  }
+  __device__ static int gchunk(bool kcol, int kq, int i, int lane) {
+    if (kcol) {
+      const int r = 16 * i + (lane >> 2), p = lane & 3;
+      return r * 16 + 4 * kq + col_pos(r, p);
+    }
+    const int kr = 4 * i + (lane >> 4), p = lane & 15;
+    return (16 * kq + kr) * 16 + row_pos(kr, p);
+  }
+};
 
 // One quarter of MFMAs for the wave's 64 x 64 block: 4 x 4 accumulator tiles,
 // k = 4 g + s (lane group g = lane / 16, MFMA s = 0..3), fragments read in
-// pairs s = 2 sp, 2 sp + 1.  The orientation of each operand is a run-time
-// choice of per-lane offsets (one code path: the accumulators stay in place);
-// a kcol pair is the two halves of one 16-byte chunk (second at +8), a krow
-// pair two k-rows (second at +512).  Every read is one byte offset from the
-// stage array: the compiler tells reads of one stage from the loads still
-// landing in the other only for addresses it can trace to the array in a few
-// steps.
-__device__ __forceinline__ int frag_off(bool kcol, int r, int k) {
-  return kcol ? 16 * (r * 8 + qcol_pos(r, k >> 1)) : 8 * (k * 64 + qrow_pos(k, r >> 1) * 2 + (r & 1));
-}
-
+// pairs s = 2 sp, 2 sp + 1 and widened from the stored TI to FP64.
+// The orientation of each operand is a run-time choice of per-lane offsets
+// (one code path: the accumulators stay in place).  Every read is one byte
+// offset from the stage array: the compiler tells reads of one stage from the
+// loads still landing in the other only for addresses it can trace to the
+// array in a few steps.
+template <typename TI>
 __device__ __forceinline__ void mma_quarter(d4 (&acc)[4][4], const char *st, int oa, int ob, bool ka, bool kb,
                                             bool na, bool nb, int lane) {
+  using G = QGeom<TI>;
   const int l16 = lane & 15;
-  const int da = ka ? 8 : 512, db = kb ? 8 : 512;
+  const int da = ka ? G::PAIR_KCOL : G::PAIR_KROW, db = kb ? G::PAIR_KCOL : G::PAIR_KROW;
 #pragma unroll
   for (int sp = 0; sp < 2; ++sp) {
     const int k = 4 * (lane >> 4) + 2 * sp;
     double fa[4][2], fb[4][2];
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
-      const int o = oa + frag_off(ka, 16 * m + l16, k);
-      fa[m][0] = *reinterpret_cast<const double *>(st + o);
-      fa[m][1] = *reinterpret_cast<const double *>(st + o + da);
+      const int o = oa + G::frag(ka, 16 * m + l16, k);
+      fa[m][0] = (double)*reinterpret_cast<const TI *>(st + o);
+      fa[m][1] = (double)*reinterpret_cast<const TI *>(st + o + da);
       if (na) {
         fa[m][0] = -fa[m][0];
         fa[m][1] = -fa[m][1];
@@ -81,9 +121,9 @@ __device__ __forceinline__ void mma_quarter(d4 (&acc)[4][4], const char *st, int
     }
 #pragma unroll
     for (int n = 0; n < 4; ++n) {
-      const int o = ob + frag_off(kb, 16 * n + l16, k);
-      fb[n][0] = *reinterpret_cast<const double *>(st + o);
-      fb[n][1] = *reinterpret_cast<const double *>(st + o + db);
+      const int o = ob + G::frag(kb, 16 * n + l16, k);
+      fb[n][0] = (double)*reinterpret_cast<const TI *>(st + o);
+      fb[n][1] = (double)*reinterpret_cast<const TI *>(st + o + db);
       if (nb) {
         fb[n][0] = -fb[n][0];
         fb[n][1] = -fb[n][1];
@@ -103,10 +143,16 @@ __device__ __forceinline__ void mma_quarter(d4 (&acc)[4][4], const char *st, int
 // FULL (with GEN, one pass): general storage, X and Y blocks read as stored
 // (X by its direct map, Y by the map of its transpose), output blocks of both
 // triangles.
-template <typename TO, bool GEN, bool FULL = false>
+// TI: stored operand values (double, or float: FP32 storage, widened to
+// FP64 at the fragment reads); TO: stored result.
+template <typename TI, typename TO, bool GEN, bool FULL = false>
 __global__ __launch_bounds__(256, 2) void k_square_f64_lds(TileArgs a) {
-  __shared__ __align__(16) double S0[4][QS];  // even quarters: A0, A1, B0, B1
-  __shared__ __align__(16) double S1[4][QS];  // odd quarters
+  using G = QGeom<TI>;
+  // even quarters in S0, odd ones in S1: operands A0, A1, B0, B1 at w G::BYTES
+  // (arrays sized for FP64 operands whatever TI is: a stage size that depends
+  // on the template argument leaves the host-side launch stub undefined)
+  __shared__ __align__(16) char S0[4 * QGeom<double>::BYTES];
+  __shared__ __align__(16) char S1[4 * QGeom<double>::BYTES];
   const int64_t t = xcd_tile(a);
   if (t < 0) return;
   const int nbr = a.nbr, W = a.W;
@@ -203,32 +249,26 @@ __global__ __launch_bounds__(256, 2) void k_square_f64_lds(TileArgs a) {
   };
 
   // quarter kq (k = 16 kq .. 16 kq + 15) of operand w of q into stage st:
-  // eight load instructions of 1 KB (8 kcol rows or 2 krow rows each)
-  const double *xp = static_cast<const double *>(a.xpool);
-  const double *yp = static_cast<const double *>(GEN ? a.ypool : a.xpool);
-  auto dma = [&](const StK &q, int kq, double (*st)[QS]) {
+  // G::LOADS load instructions of 1 KB
+  const TI *xp = static_cast<const TI *>(a.xpool);
+  const TI *yp = static_cast<const TI *>(GEN ? a.ypool : a.xpool);
+  auto dma = [&](const StK &q, int kq, char *st) {
     const int32_t so = q.sd >= 0 ? q.sd : 0;  // absent: slot 0, never multiplied
-    const double *pool = ((wave < 2) == !(GEN && q.kp)) ? xp : yp;
+    const TI *pool = ((wave < 2) == !(GEN && q.kp)) ? xp : yp;
     const char *blkp = reinterpret_cast<const char *>(pool + (int64_t)so * BB);
-    char *dst = reinterpret_cast<char *>(&st[wave][0]);
+    char *dst = st + wave * G::BYTES;
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      int gchunk;
-      if (q.kd) {
-        const int r = 8 * i + (lane >> 3), p = lane & 7;
-        gchunk = r * 32 + 8 * kq + qcol_pos(r, p);
-      } else {
-        const int kr = 2 * i + (lane >> 5), p = lane & 31;
-        gchunk = (16 * kq + kr) * 32 + qrow_pos(kr, p);
-      }
-      __builtin_amdgcn_global_load_lds(blkp + gchunk * 16, dst + i * 1024, 16, 0, 0);
+    for (int i = 0; i < G::LOADS; ++i) {
+      // the chunk index is taken into a local first: with the template-dependent
+      // call inside the builtin's arguments the host pass drops the kernel's stub
+      const int gc = G::gchunk(q.kd, kq, i, lane);
+      __builtin_amdgcn_global_load_lds(blkp + gc * 16, dst + i * 1024, 16, 0, 0);
     }
   };
 
-  auto compute = [&](const StK &q, double (*st)[QS]) {
+  auto compute = [&](const StK &q, const char *st) {
     if (pos < 0 || q.sa < 0 || q.sb < 0) return;
-    mma_quarter(acc, reinterpret_cast<const char *>(st), ia * QS * 8, (2 + jb) * QS * 8, q.ka, q.kb, GEN && q.na,
-                GEN && q.nb, lane);
+    mma_quarter<TI>(acc, st, ia * G::BYTES, (2 + jb) * G::BYTES, q.ka, q.kb, GEN && q.na, GEN && q.nb, lane);
   };
 
   // quarters of K alternate between the stages; each iteration of the loop
@@ -260,28 +300,27 @@ __global__ __launch_bounds__(256, 2) void k_square_f64_lds(TileArgs a) {
       h ^= 1;
     }
   }
+  if (pos < 0) return;
+  const auto rowf = [](int g, int v) { return MF<double>::row(g, v); };
   // the block's sums over rows 0..31 and 32..63 separately, added in that
   // order (the same rounding as two waves of 32 rows each)
-  if (pos >= 0) {
-    const auto rowf = [](int g, int v) { return MF<double>::row(g, v); };
-    d4 lo[2][4], hi[2][4];
+  d4 lo[2][4], hi[2][4];
 #pragma unroll
-    for (int m = 0; m < 2; ++m)
+  for (int m = 0; m < 2; ++m)
 #pragma unroll
-      for (int n = 0; n < 4; ++n) {
-        lo[m][n] = acc[m][n];
-        hi[m][n] = acc[2 + m][n];
-      }
-    const EpiSums p0 = epilogue_rows<double, TO, 2>(lo, a, I, J, pos, 0, rowf);
-    const EpiSums p1 = epilogue_rows<double, TO, 2>(hi, a, I, J, pos, 32, rowf);
-    if (lane == 0) {
-      double *p = a.parts + (int64_t)pos * NPART;
-      p[0] = p0.e2 + p1.e2;
-      p[1] = p0.tx + p1.tx;
-      p[2] = p0.ts + p1.ts;
-      p[3] = p0.nr + p1.nr;
-      p[4] = (double)nk;
+    for (int n = 0; n < 4; ++n) {
+      lo[m][n] = acc[m][n];
+      hi[m][n] = acc[2 + m][n];
     }
+  const EpiSums p0 = epilogue_rows<TI, TO, 2>(lo, a, I, J, pos, 0, rowf);
+  const EpiSums p1 = epilogue_rows<TI, TO, 2>(hi, a, I, J, pos, 32, rowf);
+  if (lane == 0) {
+    double *p = a.parts + (int64_t)pos * NPART;
+    p[0] = p0.e2 + p1.e2;
+    p[1] = p0.tx + p1.tx;
+    p[2] = p0.ts + p1.ts;
+    p[3] = p0.nr + p1.nr;
+    p[4] = (double)nk;
   }
 }
 
@@ -289,22 +328,30 @@ __global__ __launch_bounds__(256, 2) void k_square_f64_lds(TileArgs a) {
 
 void launch_square_f64_lds(Ctx &c, const TileArgs &a) {
   if (a.ntiles <= 0) return;
-  if (a.xprec != P64 || a.tb != 2) fail(SP2_ERR_INVALID_ARG, "FP64 LDS-load square: FP64 operands, 2 x 2 tiles");
+  if (a.tb != 2) fail(SP2_ERR_INVALID_ARG, "FP64 LDS-load square: 2 x 2 tiles");
   const bool gen = a.ypool != a.xpool || a.npass != 1 || a.xanti || a.yanti;
   if (gen && !(a.ypool && a.yidxmap && a.ybits && (a.npass == 1 || a.npass == 2)))
     fail(SP2_ERR_INVALID_ARG, "tiled product: incomplete second operand");
   const unsigned g = (unsigned)(8 * a.xcd_chunk);
-  if (a.full) {
+  if (a.xprec == P32) {
+    // FP32-stored operands, FP32 result (the FP64 tail of an expansion whose
+    // FP64 iterates do not fit in device memory)
+    if (gen || a.full || a.oprec != P32)
+      fail(SP2_ERR_INVALID_ARG, "FP64 square of FP32 values: square only, FP32 result");
+    k_square_f64_lds<float, float, false><<<g, 256, 0, c.stream>>>(a);
+  } else if (a.xprec != P64) {
+    fail(SP2_ERR_INVALID_ARG, "FP64 LDS-load square: FP64 or FP32 operands");
+  } else if (a.full) {
     if (!(a.ypool && a.yidxmap && a.ybits) || a.npass != 1 || a.xanti || a.yanti || a.oprec != P64)
       fail(SP2_ERR_INVALID_ARG, "general-storage product: one pass, FP64 output, both operands");
-    k_square_f64_lds<double, true, true><<<g, 256, 0, c.stream>>>(a);
+    k_square_f64_lds<double, double, true, true><<<g, 256, 0, c.stream>>>(a);
   } else if (a.oprec == P32) {  // FP64 arithmetic, result rounded to FP32 (the correction's commutator)
     if (!gen) fail(SP2_ERR_INVALID_ARG, "FP64 square with FP32 output is for products only");
-    k_square_f64_lds<float, true><<<g, 256, 0, c.stream>>>(a);
+    k_square_f64_lds<double, float, true><<<g, 256, 0, c.stream>>>(a);
   } else if (gen) {
-    k_square_f64_lds<double, true><<<g, 256, 0, c.stream>>>(a);
+    k_square_f64_lds<double, double, true><<<g, 256, 0, c.stream>>>(a);
   } else {
-    k_square_f64_lds<double, false><<<g, 256, 0, c.stream>>>(a);
+    k_square_f64_lds<double, double, false><<<g, 256, 0, c.stream>>>(a);
   }
   SP2_LAUNCH_CHECK();
 }

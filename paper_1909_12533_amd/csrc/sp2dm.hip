@@ -278,9 +278,9 @@ int tile_edge(int mode, int64_t nout, int nbr) {
   return (double)nout >= 0.35 * 0.5 * (double)nbr * (double)(nbr + 1) ? 4 : 2;
 }
 
-// FP64 squares and pair products run k_square_f64_lds (operands loaded
-// straight to LDS, bit-identical to k_square_tile); SP2_F64_KERNEL=tile in
-// the environment selects k_square_tile instead.
+// FP64 squares and products run k_square_f64_lds (operands loaded straight
+// to LDS, bit-identical to k_square_tile, also for FP32-stored operands);
+// SP2_F64_KERNEL=tile in the environment selects k_square_tile instead.
 bool use_f64_lds() {
   const char *e = std::getenv("SP2_F64_KERNEL");
   return !(e && e[0] == 't');
@@ -351,7 +351,7 @@ SquareOut square_step(Ctx &c, const DMat &X, const Maps &m, int mode, int oprec,
     r.plan_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   }
   SP2_HIP(hipEventRecord(ev.a, c.stream));
-  if (mode == M_F64 && oprec == P64 && ta.xprec == P64 && tb == 2 && use_f64_lds())
+  if (mode == M_F64 && tb == 2 && use_f64_lds())
     launch_square_f64_lds(c, ta);
   else
     launch_square_tile(c, mode, ta);

@@ -238,6 +238,27 @@ def test_fp32_stored_fp64_tail(gpu_lib, l8_oracle, prec):
     assert homo <= r.homo_est + 1e-9 and r.lumo_est - 1e-9 <= lumo
 
 
+def test_fp32_stored_tail_lds_kernel_bitwise(gpu_lib, monkeypatch, l8_oracle):
+    """The FP64 squares of FP32-stored iterates in the LDS-loaded kernel
+    (FP32 quarter slices widened to FP64 at the fragment reads) and in the
+    register-staged one give the same expansion bit for bit."""
+    sp2 = gpu_lib
+    Fh, Fd, no, lmin, lmax, lam, ref = l8_oracle
+    F = sp2.BsrMatrix.from_host(Fh)
+    kw = dict(trunc_norm="frobinf", tau_fixed=1e-6, coarse_bs=512, precision="fp32", tail_storage=1)
+    out = {}
+    for k in ("tile", "lds"):
+        if k == "tile":
+            monkeypatch.setenv("SP2_F64_KERNEL", "tile")
+        else:
+            monkeypatch.delenv("SP2_F64_KERNEL", raising=False)
+        r = sp2.density(F, no, lmin, lmax, -0.31, 0.33, **kw)
+        out[k] = (r.D.val.cpu().numpy(), r.iters["e"].copy(), r.n_iter, r.switch_iter)
+    assert out["tile"][2:] == out["lds"][2:] and out["lds"][3] >= 1
+    assert np.array_equal(out["tile"][1], out["lds"][1])
+    assert np.array_equal(out["tile"][0].view(np.uint64), out["lds"][0].view(np.uint64))
+
+
 def test_tail_storage_invalid(gpu_lib, l8_oracle):
     sp2 = gpu_lib
     Fh, Fd, no, lmin, lmax, lam, ref = l8_oracle
