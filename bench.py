@@ -457,9 +457,10 @@ def main():
     ap.add_argument("--corr-mcweeny", type=int, default=1,
                     help="1 (default): purify with one McWeeny step (an FP64 square and a low-precision product); "
                          "0: FP64 squares X^2, 2X - X^2")
-    ap.add_argument("--corr-deriv-tol", type=float, default=0.1,
-                    help="the correction's derivative steps stop at the first X~_k with e_k below this (default 0.1: "
-                         "at N = 32,000 and 108,000 the last two steps change ||D - D_FP64||_F by under 1e-6)")
+    ap.add_argument("--corr-deriv-tol", type=float, default=0.2,
+                    help="the correction's derivative steps stop at the first X~_k with e_k below this (default 0.2: "
+                         "at N = 108,000 the last four steps, two of them at e_k = 0.12-0.17, change "
+                         "||D - D_FP64||_F by under 1e-6; the McWeeny purification projects the rest)")
     ap.add_argument("--corr-low-floor-stop", type=int, default=1,
                     help="with the correction: the low-precision expansion stops at the first e_i below ten times "
                          "its rounding noise (1, default) or by the criterion of Algorithm 2 (0)")
