@@ -661,6 +661,8 @@ def main():
                     "expansion's block-sparse flops / time to D of one solve (sum of its steps)",
             "alg_tflop_expansion": round(exp_flops / 1e12, 3),
             "device_peak_gb": round(res.correction["device_peak_bytes"] / 1e9, 2),
+            # the library options of the timed solve (beyond the Frob-Inf truncation above)
+            "options": {k: v for k, v in mopts.items() if k != "precision"},
         },
         "checks": checks,
         "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK[prec], "unit": "TFLOP/s",
