@@ -73,10 +73,11 @@ def test_fp64_matches_oracle_l12(gpu_lib, l12):
                                                ("bf16x3", 1, True)])
 def test_corrected_low_precision_matches_oracle_l12(gpu_lib, l12, prec, mcweeny, fast):
     """fast: the benchmark's settings (the expansion stops at its noise floor,
-    derivative steps stop at e_k < 0.2)."""
+    derivative steps stop at e_k < 0.2, the correction's intermediates are
+    truncated within a Frobenius budget of 3e-7 each)."""
     sp2 = gpu_lib
     Fh, no, lmin, lmax, h, lu, ref = l12
-    extra = dict(low_floor_stop=1, corr_deriv_tol=0.2) if fast else {}
+    extra = dict(low_floor_stop=1, corr_deriv_tol=0.2, corr_tol=3e-7) if fast else {}
     r = sp2.density(sp2.BsrMatrix.from_host(Fh), no, lmin, lmax, h, lu, precision=prec, switch_tol=0.0,
                     correct=1, corr_mcweeny=mcweeny, corr_purify=1 if mcweeny else 2, **extra, **KW)
     D = to_dense(r.D)
