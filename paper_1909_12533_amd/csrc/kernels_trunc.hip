@@ -175,6 +175,57 @@ __global__ void k_seg_select(const int32_t *idx, const int64_t *start, const int
   seg_cnt[s] = cnt;
 }
 
+// The same selection with one workgroup per segment, for few long segments
+// (the Frobenius norm has one segment over the whole matrix): the squared
+// norms of the next SEL candidates are gathered into LDS by all threads at
+// once, and thread 0 adds them in sorted order exactly as k_seg_select does
+// (same expression, same order, same stopping test), so the removed set and
+// the segment error are the same bits; the gather latency is paid once per
+// SEL candidates instead of once per candidate.
+constexpr int SEL = 256;
+__global__ __launch_bounds__(SEL) void k_seg_select_wg(const int32_t *idx, const int64_t *start, const int64_t *end,
+                                                       int nseg, const double *nrm2, const double *budget,
+                                                       const double *segw, int64_t *keep, double *seg_err,
+                                                       int64_t *seg_cnt) {
+  __shared__ double v[SEL];
+  __shared__ int taken, stopped;
+  const int s = blockIdx.x;
+  if (s >= nseg) return;
+  const int64_t p1 = end[s];
+  const double bud = budget[s], wt = segw[s];
+  double acc = 0.0;  // thread 0's running sum
+  int64_t cnt = 0;
+  for (int64_t base = start[s]; base < p1; base += SEL) {
+    const int64_t p = base + threadIdx.x;
+    if (p < p1) v[threadIdx.x] = nrm2[idx[p]];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const int n = (int)(p1 - base < SEL ? p1 - base : SEL);
+      int t = 0;
+      for (; t < n; ++t) {
+        const double nxt = acc + wt * v[t];
+        if (nxt <= bud)
+          acc = nxt;
+        else
+          break;
+      }
+      cnt += t;
+      taken = t;
+      stopped = t < n ? 1 : 0;
+    }
+    __syncthreads();
+    const int tk = taken;
+    const bool stop = stopped != 0;
+    if ((int)threadIdx.x < tk) keep[idx[p]] = 0;
+    __syncthreads();  // taken / stopped and v are rewritten in the next round
+    if (stop) break;
+  }
+  if (threadIdx.x == 0) {
+    seg_err[s] = acc;
+    seg_cnt[s] = cnt;
+  }
+}
+
 __global__ void k_gather_rowptr(const int64_t *row_ptr, const int64_t *pos, int nbr, int64_t *out) {
   const int I = blockIdx.x * blockDim.x + threadIdx.x;
   if (I > nbr) return;
@@ -327,9 +378,16 @@ void truncate_select(Ctx &c, const Pattern &pat, const double *nrm2, double tau,
     k_seg_bounds<<<blocks_for(ncand), TPB, 0, c.stream>>>(sa, ncand, st.as<int64_t>(), en.as<int64_t>());
     SP2_LAUNCH_CHECK();
     Buf serr = c.alloc(sizeof(double) * nseg), scnt = c.alloc(sizeof(int64_t) * nseg);
-    k_seg_select<<<blocks_for(nseg, 64), 64, 0, c.stream>>>(ia, st.as<int64_t>(), en.as<int64_t>(), nseg, nrm2,
+    // few segments (the Frobenius norm, coarse Frob-Inf partitions): a
+    // workgroup each; many short ones: a thread each (same result)
+    if (nseg <= 16384)
+      k_seg_select_wg<<<(unsigned)nseg, SEL, 0, c.stream>>>(ia, st.as<int64_t>(), en.as<int64_t>(), nseg, nrm2,
                                                              d_budget.as<double>(), d_segw.as<double>(), keep,
                                                              serr.as<double>(), scnt.as<int64_t>());
+    else
+      k_seg_select<<<blocks_for(nseg, 64), 64, 0, c.stream>>>(ia, st.as<int64_t>(), en.as<int64_t>(), nseg, nrm2,
+                                                               d_budget.as<double>(), d_segw.as<double>(), keep,
+                                                               serr.as<double>(), scnt.as<int64_t>());
     SP2_LAUNCH_CHECK();
     std::vector<int64_t> cnt(nseg);
     c.d2h(out.seg_err.data(), serr.p, sizeof(double) * nseg);
