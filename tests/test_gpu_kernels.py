@@ -98,6 +98,28 @@ def test_truncate_matches_oracle(gpu_lib, norm, cbs, tau):
     assert np.array_equal(to_dense(Xt), Xt_ref)
 
 
+@pytest.mark.parametrize("norm,cbs", [("frob", 4096), ("frobinf", 4096)])
+@pytest.mark.parametrize("tau", [1e-2, 1e-1])
+def test_truncate_long_segments_match_oracle(gpu_lib, norm, cbs, tau):
+    """Segments with more candidates than one gather round of the selection
+    (256): over a thousand upper blocks in one segment, the budget running
+    out after the first round; same removed set, error and values as the
+    oracle."""
+    sp2 = gpu_lib
+    Mh = _spread_bsr(3300, seed=11)
+    Md = bsr_to_dense(Mh)
+    mask = np.zeros((Mh.nbr, Mh.nbr), dtype=bool)
+    mask[Mh.rows(), Mh.col_idx] = True
+    mask = mask | mask.T
+    Xt_ref, Mt_ref, info = O.truncate(Md, mask, tau, norm, 64, cbs)
+    assert Mh.nnzb > 1000 and info.removed > 256
+    Xt, err = sp2.truncate(sp2.BsrMatrix.from_host(Mh), tau, norm, cbs)
+    assert np.array_equal(upper_mask(Xt), np.triu(Mt_ref)), "removed block sets differ"
+    assert err[0] == pytest.approx(info.err_frob, rel=1e-12, abs=1e-300)
+    assert err[1] == pytest.approx(info.err_mixed, rel=1e-12, abs=1e-300)
+    assert np.array_equal(to_dense(Xt), Xt_ref)
+
+
 def test_truncate_ties_in_block_order(gpu_lib):
     """Equal block norms are removed in (I, J) order."""
     sp2 = gpu_lib
